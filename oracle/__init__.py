@@ -1,0 +1,390 @@
+"""CPU oracle for ESG range-filtered k-NN search -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the bench
+may import this package.  It shares no code with the product (the HIP
+library and its Python binding): it reads index files with its own reader,
+encodes bfloat16 / fp8 with its own encoders written from the format
+definitions, and runs the plain C routines of ``esg_oracle.c``.
+
+Contents and the passage each follows:
+
+* ``read_index``          -- own reader of the documented index file layout.
+* ``select``              -- Alg. 4 subrange selection (Section 4.2).
+* ``elastic_factor``      -- Def. 3.1 over the recorded ranges of the tree.
+* ``cd32/cd16/cd8``       -- squared Euclidean distance (Section 2.1) in
+                             float32 with the fixed summation order.
+* ``search_part``         -- Alg. 1 + POST (Sections 2.1, 2.2) on one node.
+* ``query/query_batch``   -- Alg. 4 end to end (select, search/scan, merge).
+* ``bruteforce``          -- Def. 2.1 / 2.2 exact filtered k-NN in float64.
+* ``recall``              -- recall@k against exact ground truth, counting a
+                             returned point as correct when its exact
+                             distance does not exceed the k-th true one.
+* ``bf16_encode`` / ``e4m3_encode`` -- storage codecs (round to nearest
+                             even; fp8 OCP E4M3 with a per-vector scale).
+* ``mlp_*``               -- float64 forward and manual backward of the
+                             12-64-64-1 ReLU network that predicts ef.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import struct
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "esg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+KIND_GRAPH, KIND_SCAN = 1, 2
+DIST_F32, DIST_BF16, DIST_FP8 = 0, 1, 2
+NO_NODE = 0xFFFFFFFF
+
+
+def compile_oracle(force: bool = False) -> str:
+    """Compile esg_oracle.c into liboracle.so (no fast-math, no contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fopenmp", "-shared", "-fPIC", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        # ESG_ORACLE_LIB points the tests' mutation checks at a deliberately
+        # broken copy of the oracle.
+        path = os.environ.get("ESG_ORACLE_LIB") or compile_oracle()
+        _lib = ctypes.CDLL(path)
+        _declare(_lib)
+    return _lib
+
+
+class _Index(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("r", ctypes.c_int32),
+                ("n_depth", ctypes.c_int32), ("leaf", ctypes.c_int32), ("c_den", ctypes.c_int32),
+                ("pad_", ctypes.c_int32),
+                ("vec", ctypes.c_void_p), ("vec16", ctypes.c_void_p), ("vec8", ctypes.c_void_p),
+                ("scale8", ctypes.c_void_p), ("adj", ctypes.c_void_p), ("ep", ctypes.c_void_p),
+                ("ext_id", ctypes.c_void_p)]
+
+
+def _declare(L):
+    i64, i32, vp, f32 = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_float
+    L.oracle_select.argtypes = [i64, i64, i32, i64, i64, vp, i32]
+    L.oracle_select.restype = i32
+    L.oracle_elastic_ok.argtypes = [i64, i64, i64, i64, i32]
+    L.oracle_elastic_ok.restype = i32
+    L.oracle_elastic_factor.argtypes = [i64, i64, i64, i64, vp, vp]
+    L.oracle_elastic_factor.restype = i32
+    L.oracle_cd32.argtypes = [vp, vp, i32]
+    L.oracle_cd32.restype = f32
+    L.oracle_cd16.argtypes = [vp, vp, i32]
+    L.oracle_cd16.restype = f32
+    L.oracle_cd8.argtypes = [vp, f32, vp, i32]
+    L.oracle_cd8.restype = f32
+    L.oracle_e4m3_value.argtypes = [ctypes.c_uint8]
+    L.oracle_e4m3_value.restype = f32
+    L.oracle_search_part.argtypes = [vp, i32, i64, i64, i64, i64, i64, vp, i32, i64, i64, i32,
+                                     vp, vp, vp, vp, i64, vp, vp]
+    L.oracle_search_part.restype = i32
+    L.oracle_scan_part.argtypes = [vp, i64, i64, vp, i32, vp, vp, vp]
+    L.oracle_scan_part.restype = i32
+    L.oracle_query.argtypes = [vp, vp, i64, i64, i32, i32, i64, i64, i32, i32, vp, vp, vp]
+    L.oracle_query.restype = i32
+    L.oracle_query_batch.argtypes = [vp, vp, vp, vp, i64, i32, i32, i64, i64, i32, i32,
+                                     vp, vp, vp, vp]
+    L.oracle_query_batch.restype = i32
+    L.oracle_bruteforce.argtypes = [vp, i64, i32, vp, i64, i64, i32, vp, vp]
+    L.oracle_bruteforce.restype = i32
+    L.oracle_bruteforce_batch.argtypes = [vp, i64, i32, vp, vp, vp, i64, i32, vp, vp, vp]
+    L.oracle_bruteforce_batch.restype = i32
+
+
+def _p(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+# --------------------------------------------------------------------------
+# Index file reader (layout documented with the C ABI, version 1).
+# --------------------------------------------------------------------------
+
+class OracleIndex:
+    """Arrays of one index in host memory plus the C view the oracle uses."""
+
+    def __init__(self, n, d, degree, leaf, n_depth, c_den, ext_id, attr, vec, adj, ep):
+        self.n, self.d, self.degree, self.leaf = int(n), int(d), int(degree), int(leaf)
+        self.n_depth, self.c_den = int(n_depth), int(c_den)
+        self.ext_id = np.ascontiguousarray(ext_id, dtype=np.int64)
+        self.attr = np.ascontiguousarray(attr, dtype=np.float64)
+        self.vec = np.ascontiguousarray(vec, dtype=np.float32)
+        self.adj = np.ascontiguousarray(adj, dtype=np.uint32)
+        self.ep = np.ascontiguousarray(ep, dtype=np.uint32)
+        self.vec16 = None
+        self.vec8 = None
+        self.scale8 = None
+        self._c = None
+
+    def with_bf16(self):
+        self.vec16 = bf16_encode(self.vec)
+        self._c = None
+        return self
+
+    def with_fp8(self):
+        self.vec8, self.scale8 = e4m3_encode_rows(self.vec)
+        self._c = None
+        return self
+
+    def cstruct(self):
+        if self._c is None:
+            s = _Index()
+            s.n, s.d, s.r, s.n_depth = self.n, self.d, self.degree, self.n_depth
+            s.leaf, s.c_den, s.pad_ = self.leaf, self.c_den, 0
+            s.vec, s.vec16, s.vec8 = _p(self.vec), _p(self.vec16), _p(self.vec8)
+            s.scale8, s.adj, s.ep, s.ext_id = _p(self.scale8), _p(self.adj), _p(self.ep), _p(self.ext_id)
+            self._c = s
+        return ctypes.byref(self._c)
+
+
+def read_index(path: str) -> OracleIndex:
+    with open(path, "rb") as f:
+        head = f.read(128)
+    if len(head) < 128 or head[:8] != b"ESGIDX01":
+        raise ValueError("not an index file")
+    version, header_bytes = struct.unpack_from("<II", head, 8)
+    n, = struct.unpack_from("<q", head, 16)
+    d, degree, leaf, fanout, n_depth, c_den, efc, _ = struct.unpack_from("<8i", head, 24)
+    off_ids, off_attr, off_vec, off_adj, off_ep, file_bytes = struct.unpack_from("<6Q", head, 56)
+    if version != 1 or fanout != 2:
+        raise ValueError("unsupported index version/fanout")
+    mm = np.memmap(path, dtype=np.uint8, mode="r")
+    if mm.size != file_bytes:
+        raise ValueError("truncated index file")
+
+    def sect(off, dtype, count):
+        return np.frombuffer(mm, dtype=dtype, count=count, offset=off)
+
+    ext_id = sect(off_ids, np.int64, n)
+    attr = sect(off_attr, np.float64, n)
+    vec = sect(off_vec, np.float32, n * d).reshape(n, d)
+    adj = sect(off_adj, np.uint32, n_depth * n * degree).reshape(n_depth, n, degree)
+    ep = sect(off_ep, np.uint32, 1 << n_depth)
+    return OracleIndex(n, d, degree, leaf, n_depth, c_den, ext_id, attr, vec, adj, ep)
+
+
+# --------------------------------------------------------------------------
+# Codecs, written from the format definitions.
+# --------------------------------------------------------------------------
+
+def bf16_encode(x: np.ndarray) -> np.ndarray:
+    """float32 -> bfloat16 bit patterns, round to nearest, ties to even.
+
+    Written from the definition: the two bfloat16 values that bracket x are
+    the truncation t (drop the low 16 bits) and the next one up in
+    magnitude; pick the nearer in exact (float64) arithmetic and, on a tie,
+    the one whose last kept bit is 0.  Inputs are finite."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    bits = x.view(np.uint32)
+    lo = (bits & np.uint32(0xFFFF0000))
+    hi = lo + np.uint32(0x10000)
+    vlo = lo.view(np.float32).astype(np.float64)
+    vhi = hi.view(np.float32).astype(np.float64)
+    xv = x.astype(np.float64)
+    dlo = np.abs(xv - vlo)
+    dhi = np.abs(vhi - xv)
+    lo_even = ((lo >> np.uint32(16)) & np.uint32(1)) == 0
+    pick_hi = (dhi < dlo) | ((dhi == dlo) & ~lo_even)
+    out = np.where(pick_hi, hi, lo) >> np.uint32(16)
+    return out.astype(np.uint16)
+
+
+def bf16_decode(h: np.ndarray) -> np.ndarray:
+    return (h.astype(np.uint32) << np.uint32(16)).view(np.float32)
+
+
+def _e4m3_table() -> np.ndarray:
+    L = lib()
+    return np.array([L.oracle_e4m3_value(c) for c in range(256)], dtype=np.float32)
+
+
+_E4M3 = None
+
+
+def e4m3_values() -> np.ndarray:
+    global _E4M3
+    if _E4M3 is None:
+        _E4M3 = _e4m3_table()
+    return _E4M3
+
+
+def e4m3_encode(y: np.ndarray) -> np.ndarray:
+    """float32 -> OCP E4M3 codes: nearest representable value, ties to the
+    code with an even mantissa, magnitudes beyond 448 saturate to +-448.
+    Brute force over the 126 finite non-negative magnitudes."""
+    y = np.asarray(y, dtype=np.float32)
+    vals = e4m3_values()
+    mags = vals[:127].astype(np.float64)          # codes 0..126: 0 .. 448 ascending
+    a = np.minimum(np.abs(y.astype(np.float64)), 448.0)
+    i = np.searchsorted(mags, a, side="left")      # mags[i-1] < a <= mags[i]
+    i = np.clip(i, 1, 126)
+    below, above = mags[i - 1], mags[i]
+    d_lo, d_hi = a - below, above - a
+    take_hi = (d_hi < d_lo) | ((d_hi == d_lo) & ((i & 1) == 0))
+    code = np.where(take_hi, i, i - 1)
+    code = np.where(a == 0.0, 0, code)
+    sign = (np.signbit(y) & (code != 0)).astype(np.uint8) << 7
+    return (code.astype(np.uint8) | sign)
+
+
+def e4m3_encode_rows(x: np.ndarray):
+    """Per-vector scale sigma = max|x| / 448 (float32; 1 for a zero vector),
+    codes = e4m3(x / sigma) with the division in float32."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    amax = np.max(np.abs(x), axis=1)
+    scale = (amax / np.float32(448.0)).astype(np.float32)
+    scale = np.where(scale > 0, scale, np.float32(1.0)).astype(np.float32)
+    y = (x / scale[:, None]).astype(np.float32)
+    return e4m3_encode(y), scale
+
+
+# --------------------------------------------------------------------------
+# Wrappers.
+# --------------------------------------------------------------------------
+
+def select(n: int, leaf: int, lq: int, rq: int, c_den: int = 2, max_parts: int = 64):
+    """Alg. 4 parts as a list of dicts (kind, depth, heap, a, b, x, y)."""
+    buf = np.zeros((max_parts, 7), dtype=np.int64)
+    cnt = lib().oracle_select(n, leaf, c_den, lq, rq, _p(buf), max_parts)
+    if cnt < 0:
+        raise ValueError(f"invalid range [{lq},{rq}] for n={n}")
+    keys = ("kind", "depth", "heap", "a", "b", "x", "y")
+    return [dict(zip(keys, map(int, buf[i]))) for i in range(min(cnt, max_parts))], cnt
+
+
+def elastic_factor(n: int, leaf: int, l: int, r: int):
+    num = np.zeros(1, np.int64)
+    den = np.zeros(1, np.int64)
+    st = lib().oracle_elastic_factor(n, leaf, l, r, _p(num), _p(den))
+    if st != 0:
+        raise ValueError("bad range")
+    return int(num[0]), int(den[0])
+
+
+def cd32(x: np.ndarray, q: np.ndarray) -> np.float32:
+    x = np.ascontiguousarray(x, np.float32)
+    q = np.ascontiguousarray(q, np.float32)
+    return np.float32(lib().oracle_cd32(_p(x), _p(q), x.size))
+
+
+def cd16(xh: np.ndarray, q: np.ndarray) -> np.float32:
+    xh = np.ascontiguousarray(xh, np.uint16)
+    q = np.ascontiguousarray(q, np.float32)
+    return np.float32(lib().oracle_cd16(_p(xh), _p(q), xh.size))
+
+
+def cd8(codes: np.ndarray, scale: float, q: np.ndarray) -> np.float32:
+    codes = np.ascontiguousarray(codes, np.uint8)
+    q = np.ascontiguousarray(q, np.float32)
+    return np.float32(lib().oracle_cd8(_p(codes), float(scale), _p(q), codes.size))
+
+
+def search_part(ix: OracleIndex, part: dict, q: np.ndarray, m: int, cap_p: int | None = None,
+                hop_budget: int = -1, kind: int = DIST_F32, visited_cap: int = 1 << 22):
+    """Alg. 1 + POST on the node of ``part``.  Returns (dists, positions,
+    visited (discovery order), hops, status)."""
+    q = np.ascontiguousarray(q, np.float32)
+    cap_p = m if cap_p is None else cap_p
+    qd = np.zeros(m, np.float32)
+    qp = np.zeros(m, np.int64)
+    ql = np.zeros(1, np.int32)
+    vis = np.zeros(visited_cap, np.int64)
+    nv = np.zeros(1, np.int64)
+    hops = np.zeros(1, np.int64)
+    st = lib().oracle_search_part(ix.cstruct(), part["depth"], part["heap"], part["a"], part["b"],
+                                  part["x"], part["y"], _p(q), m, cap_p, hop_budget, kind,
+                                  _p(qd), _p(qp), _p(ql), _p(vis), visited_cap, _p(nv), _p(hops))
+    L = int(ql[0])
+    return qd[:L], qp[:L], vis[:min(int(nv[0]), visited_cap)], int(hops[0]), st
+
+
+def query(ix: OracleIndex, q, lq, rq, k, ef, cap_p=None, hop_budget=-1, kind=DIST_F32, rerank=0):
+    q = np.ascontiguousarray(q, np.float32)
+    ids = np.zeros(k, np.int64)
+    dists = np.zeros(k, np.float32)
+    stats = np.zeros(8, np.int64)
+    st = lib().oracle_query(ix.cstruct(), _p(q), lq, rq, k, ef, ef if cap_p is None else cap_p,
+                            hop_budget, kind, rerank, _p(ids), _p(dists), _p(stats))
+    return ids, dists, stats, st
+
+
+def query_batch(ix: OracleIndex, Q, l, r, k, ef, cap_p=None, hop_budget=-1, kind=DIST_F32,
+                rerank=0, with_stats=False):
+    Q = np.ascontiguousarray(Q, np.float32)
+    l = np.ascontiguousarray(l, np.int64)
+    r = np.ascontiguousarray(r, np.int64)
+    nq = Q.shape[0]
+    ids = np.zeros((nq, k), np.int64)
+    dists = np.zeros((nq, k), np.float32)
+    stats = np.zeros((nq, 8), np.int64) if with_stats else None
+    status = np.zeros(nq, np.int32)
+    lib().oracle_query_batch(ix.cstruct(), _p(Q), _p(l), _p(r), nq, k, ef,
+                             ef if cap_p is None else cap_p, hop_budget, kind, rerank,
+                             _p(ids), _p(dists), _p(stats), _p(status))
+    return (ids, dists, status, stats) if with_stats else (ids, dists, status)
+
+
+def bruteforce(vec_pos: np.ndarray, Q, l, r, k):
+    """Exact filtered k-NN (float64) over position-ordered vectors.
+    Returns (positions [nq,k] (-1 pad), float64 distances [nq,k] (+inf pad))."""
+    vec_pos = np.ascontiguousarray(vec_pos, np.float32)
+    Q = np.ascontiguousarray(np.atleast_2d(Q), np.float32)
+    l = np.ascontiguousarray(np.atleast_1d(l), np.int64)
+    r = np.ascontiguousarray(np.atleast_1d(r), np.int64)
+    nq = Q.shape[0]
+    pos = np.zeros((nq, k), np.int64)
+    dist = np.zeros((nq, k), np.float64)
+    status = np.zeros(nq, np.int32)
+    n, d = vec_pos.shape
+    lib().oracle_bruteforce_batch(_p(vec_pos), n, d, _p(Q), _p(l), _p(r), nq, k,
+                                  _p(pos), _p(dist), _p(status))
+    if np.any(status != 0):
+        raise ValueError("invalid range in bruteforce")
+    return pos, dist
+
+
+def exact_dist64(vec_pos: np.ndarray, q: np.ndarray, pos: np.ndarray) -> np.ndarray:
+    """float64 squared distances of the given positions (-1 -> +inf)."""
+    pos = np.asarray(pos)
+    out = np.full(pos.shape, np.inf)
+    ok = pos >= 0
+    diff = vec_pos[pos[ok]].astype(np.float64) - np.asarray(q, np.float64)
+    out[ok] = np.sum(diff * diff, axis=-1)
+    return out
+
+
+def recall(vec_pos, Q, l, r, pos_found, gt_pos, gt_dist, k):
+    """Mean recall@k.  A returned position counts when it lies in [l,r] and
+    its float64 distance is <= the k-th exact distance (ties are credited);
+    the count is divided by min(k, r-l+1).  Also returns the strict
+    id-overlap recall."""
+    nq = Q.shape[0]
+    rec = np.zeros(nq)
+    strict = np.zeros(nq)
+    for i in range(nq):
+        w = int(r[i] - l[i] + 1)
+        kk = min(k, w)
+        found = pos_found[i][pos_found[i] >= 0]
+        found = found[(found >= l[i]) & (found <= r[i])]
+        found = np.unique(found)
+        # both sides through the same float64 routine, so equal points compare equal
+        dk = exact_dist64(vec_pos, Q[i], gt_pos[i][kk - 1:kk])[0]
+        df = exact_dist64(vec_pos, Q[i], found)
+        rec[i] = min(kk, int(np.sum(df <= dk))) / kk
+        strict[i] = len(np.intersect1d(found, gt_pos[i][:kk])) / kk
+    return float(rec.mean()), float(strict.mean()), rec

@@ -1,0 +1,67 @@
+"""Test-side helpers: small hand-checkable trees and graphs built in numpy.
+
+These build index arrays for the oracle directly (no product code): the
+segment tree of Section 4.2 enumerated breadth-first, and per node a graph
+whose rows hold the node's chain neighbours (p-1, p+1, which keeps every
+node graph connected) followed by nearest neighbours in float64."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+NO = 0xFFFFFFFF
+
+
+def tree_nodes(n: int, leaf: int):
+    """All tree nodes as (depth, heap, a, b, is_graph), breadth-first."""
+    out = []
+    todo = [(0, 1, 0, n - 1)]
+    while todo:
+        nxt = []
+        for depth, heap, a, b in todo:
+            g = (b - a) >= leaf
+            out.append((depth, heap, a, b, g))
+            if g and a < b:
+                m = (a + b) // 2
+                nxt.append((depth + 1, 2 * heap, a, m))
+                nxt.append((depth + 1, 2 * heap + 1, m + 1, b))
+        todo = nxt
+    return out
+
+
+def make_test_index(X: np.ndarray, leaf: int, R: int = 8, ep_mode: str = "first",
+                    rng: np.random.Generator | None = None) -> oracle.OracleIndex:
+    X = np.ascontiguousarray(X, np.float32)
+    n, d = X.shape
+    nodes = tree_nodes(n, leaf)
+    n_depth = max([t for t, _, _, _, g in nodes if g], default=-1) + 1
+    adj = np.full((max(n_depth, 0), n, R), NO, dtype=np.uint32)
+    ep = np.full(1 << max(n_depth, 0), NO, dtype=np.uint32)
+    X64 = X.astype(np.float64)
+    for t, h, a, b, g in nodes:
+        if not g:
+            continue
+        idx = np.arange(a, b + 1)
+        D = ((X64[idx, None, :] - X64[None, idx, :]) ** 2).sum(-1)
+        for i, p in enumerate(idx):
+            row = []
+            if p - 1 >= a:
+                row.append(p - 1)
+            if p + 1 <= b:
+                row.append(p + 1)
+            order = np.lexsort((idx, D[i]))
+            for j in order:
+                q = idx[j]
+                if len(row) >= R:
+                    break
+                if q != p and q not in row:
+                    row.append(q)
+            adj[t, p, :len(row)] = row
+        if ep_mode == "first":
+            ep[h] = a
+        else:
+            ep[h] = (rng or np.random.default_rng(h)).integers(a, b + 1)
+    ext = np.arange(n, dtype=np.int64)
+    return oracle.OracleIndex(n, d, R, leaf, n_depth, 2, ext, np.arange(n, dtype=np.float64),
+                              X, adj, ep)
