@@ -1,0 +1,188 @@
+/*
+ * esg.h -- C ABI of libesg, an MI355X (gfx950) engine for range-filtered
+ * approximate k-nearest-neighbour search with elastic graphs (ESG,
+ * Yang et al.).
+ *
+ * Problem (Def. 2.2): the database holds N vectors in R^d, each with a
+ * numeric attribute.  Points are re-ranked by attribute (footnote of
+ * Section 1), so a point's attribute rank is its *position* p in [0, N-1]
+ * (the paper's [1,N], shifted to 0-based).  A query (q, l, r) asks for the
+ * (approximate) k points nearest to q in Euclidean distance (Def. 2.1)
+ * among the positions l <= p <= r.
+ *
+ * Index (Section 4.2, HBI-2D): a fanout-2 segment tree over [0, N-1].  Node
+ * [a,b] is split at floor((a+b)/2); a node with b - a >= leaf holds a
+ * proximity graph over its points (Alg. 3); smaller nodes are scanned.
+ * A query picks at most two nodes (Alg. 4, Lemma 4.2) whose graphs cover
+ * [l,r] with ratio |part| / |node| >= 1/2 (Def. 3.1), searches each with
+ * Alg. 1 under the POST principle (Section 2.2) -- out-of-range points are
+ * traversed but never returned -- and merges the two answers.
+ *
+ * Conventions for every entry point:
+ *  - Return value 0 (ESG_OK) or a negative ESG_E* code; nothing throws or
+ *    aborts across this boundary.  esg_status_str() names the code.
+ *  - "device" pointers are HIP device memory on the index's device; "host"
+ *    pointers are ordinary CPU memory.  The caller owns every buffer it
+ *    passes; the library owns the memory behind an esg_index.
+ *  - Distances are squared Euclidean distances in float32.
+ *  - All ordering uses the pair (distance, position): ties never occur.
+ *  - An esg_index may be used by one stream at a time.
+ */
+#ifndef ESG_H_
+#define ESG_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define ESG_OK 0
+#define ESG_EINVAL (-1)      /* bad argument (null pointer, size, k/ef)     */
+#define ESG_ERANGE (-2)      /* value out of the supported range            */
+#define ESG_ENOMEM (-3)      /* host or device allocation failed            */
+#define ESG_EIO (-4)         /* file could not be opened / read / written   */
+#define ESG_EFORMAT (-5)     /* index file malformed or checksum mismatch   */
+#define ESG_EHIP (-6)        /* a HIP runtime call failed                   */
+#define ESG_EUNSUPPORTED (-7)/* feature not available for this index       */
+#define ESG_EOVERFLOW (-8)   /* a bounded device structure overflowed       */
+
+#define ESG_EF_MAX 1024      /* largest beam width m (= ef) accepted        */
+#define ESG_DEGREE_MAX 32    /* largest graph degree accepted               */
+#define ESG_NO_NODE 0xFFFFFFFFu /* padding value of an adjacency row        */
+
+/* ---- index file (version 1), little-endian ------------------------------
+ * bytes [0,512): header
+ *   char     magic[8]  = "ESGIDX01"
+ *   uint32   version   = 1, header_bytes = 512
+ *   int64    n;  int32 d, degree, leaf, fanout, n_depth, c_den, ef_construction, pad
+ *   uint64   off_ids, off_attr, off_vec, off_adj, off_ep, file_bytes
+ *   uint32   crc32c of the sections ids, attr, vec, adj, ep (in that order)
+ *   uint32   crc32c of header bytes [0,124)
+ * sections (each 4096-aligned):
+ *   ids  int64  [n]                external id of the point at position p
+ *   attr float64[n]                sorted attribute values (rank -> value)
+ *   vec  float32[n][d]             vectors in position order
+ *   adj  uint32 [n_depth][n][degree]  row p of depth t: neighbours of p in
+ *                                  the graph of the depth-t node holding p,
+ *                                  positions inside that node, ESG_NO_NODE pad
+ *   ep   uint32 [2^n_depth]        entry point of the graph node with heap
+ *                                  number h (root 1, children 2h and 2h+1),
+ *                                  ESG_NO_NODE where the node has no graph
+ * ----------------------------------------------------------------------- */
+
+typedef struct {
+  int32_t degree;          /* max out-degree R of every graph (<= 32), 16   */
+  int32_t leaf;            /* leaf bound: node [a,b] has a graph iff b-a >= leaf (>= 1) */
+  int32_t ef_construction; /* beam width of the insertion searches, 200     */
+  int32_t fanout;          /* segment-tree fanout; only 2 is supported      */
+  int32_t threads;         /* host threads, 0 = all                         */
+  int32_t batch_max;       /* largest insertion batch, 0 = default (1024)   */
+  int32_t verbose;         /* print progress to stderr                      */
+  int32_t reserved;
+} esg_build_params;
+
+/* Builds the HBI-2D index of Alg. 3 on the host and writes it to out_path.
+ * vecs: host float32 [n][d] row-major, point i = external id i.
+ * attr: host float64 [n] attribute values (any order; equal values are
+ *       ranked by external id).
+ * Each internal node's graph is a copy of its left child's graph plus the
+ * insertion of the right half (Alg. 3); a node whose left child is a leaf
+ * first builds the left half from scratch.  Insertion is a beam search of
+ * width ef_construction followed by occlusion pruning (Section 2.1) to at
+ * most `degree` neighbours and reverse edges.  Points are inserted in
+ * deterministic batches, so the file does not depend on `threads`.
+ * Errors: EINVAL (null/size), ENOMEM, EIO. */
+int32_t esg_build_index(const float* vecs, const double* attr, int64_t n, int32_t d,
+                        const esg_build_params* params, const char* out_path);
+
+/* ---- loaded index -------------------------------------------------------- */
+typedef struct esg_index esg_index;
+
+typedef struct {
+  int64_t n;
+  int32_t d, degree, leaf, fanout, n_depth, c_den;
+  int32_t has_bf16, has_fp8;  /* device copies made by esg_index_add_storage */
+  int64_t device_bytes;       /* device memory owned by the index           */
+} esg_index_info_t;
+
+/* Reads the index file, checks magic, sizes and checksums, and copies it to
+ * HIP device `hip_device` (plus the fixed search workspace).  On success
+ * *out owns all of it until esg_free_index.  Errors: EINVAL, EIO, EFORMAT,
+ * ENOMEM, EHIP. */
+int32_t esg_load_index(const char* path, int32_t hip_device, esg_index** out);
+
+/* Adds a reduced-precision traversal copy of the vectors on the device:
+ * kind 1 = bfloat16 (round to nearest even), kind 2 = fp8 OCP e4m3 with a
+ * per-vector float32 scale max|x|/448 (saturating, nearest-even).  The
+ * float32 copy stays for the rerank.  stream: hipStream_t or NULL. */
+int32_t esg_index_add_storage(esg_index* idx, int32_t kind, void* stream);
+
+/* Copies the device vectors of `kind` (0 float32 [n][d], 1 bfloat16 bits
+ * [n][d], 2 fp8 codes [n][d] followed by float32 scales [n]) to host memory
+ * `dst` of `bytes` bytes (must be exactly the size listed).  Synchronous.
+ * For inspection and tests.  Errors: EINVAL (size), EUNSUPPORTED (no such
+ * copy), EHIP. */
+int32_t esg_index_copy_storage(const esg_index* idx, int32_t kind, void* dst, int64_t bytes);
+
+int32_t esg_index_info(const esg_index* idx, esg_index_info_t* out);
+void esg_free_index(esg_index* idx);
+const char* esg_status_str(int32_t status);
+
+/* ---- search --------------------------------------------------------------
+ * queries: device float32 [nq][d] row-major
+ * l, r:    device int64 [nq], inclusive position range; a query with
+ *          l < 0, r > N-1 or l > r is invalid: its output row is all -1 /
+ *          +inf and it is counted in n_invalid (opts), the batch goes on.
+ * k, ef:   1 <= k <= ef <= ESG_EF_MAX; ef is the beam width m of Alg. 1.
+ * ids:     device int64 [nq][k] out, external ids, -1 where fewer than k
+ *          points lie in the range.
+ * dists:   device float32 [nq][k] out, squared L2, +inf padding.
+ * stream:  hipStream_t (NULL = default stream).  The call is asynchronous
+ *          with respect to the host; it never allocates memory.
+ * Errors (nothing launched): EINVAL, ERANGE (nq beyond the workspace),
+ * EHIP.  */
+int32_t esg_search_batch(esg_index* idx, const float* queries, const int64_t* l,
+                         const int64_t* r, int64_t nq, int32_t k, int32_t ef,
+                         int64_t* ids, float* dists, void* stream);
+
+#define ESG_TRAV_F32 0
+#define ESG_TRAV_BF16 1
+#define ESG_TRAV_FP8 2
+
+/* Optional per-part debug record (device memory, [nq][2] records). */
+typedef struct {
+  int32_t kind;       /* 0 none, 1 graph search, 2 leaf scan */
+  int32_t depth;
+  int64_t heap;       /* heap number of the tree node */
+  int64_t a, b;       /* node range */
+  int64_t x, y;       /* part of the query range inside the node */
+  int64_t hops;       /* expansions of Alg. 1 */
+  int64_t n_visited;  /* points whose distance was computed */
+} esg_part_trace;
+
+typedef struct {
+  int32_t traversal;     /* ESG_TRAV_*                                     */
+  int32_t rerank;        /* recompute final candidates in float32           */
+  int32_t cand_cap;      /* capacity of P (0 = ef)                          */
+  int32_t hash_cap;      /* LDS visited-hash entries per wave, a power of two
+                            in [64, 16384] (0 = 2048); beyond 3/4 of it the
+                            search continues exactly with a global bitmap  */
+  int64_t hop_budget;    /* max expansions per graph part, < 0 = unbounded  */
+  esg_part_trace* trace; /* device [nq][2] or NULL                          */
+  uint32_t* visited;     /* device [nq][2][visited_cap] or NULL: visited positions */
+  int64_t visited_cap;   /* capacity per part of `visited`                  */
+  int64_t* n_invalid;    /* device int64[1] or NULL: += invalid queries     */
+} esg_search_opts;
+
+/* esg_search_batch with options; opts == NULL behaves like esg_search_batch. */
+int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts,
+                            const float* queries, const int64_t* l, const int64_t* r,
+                            int64_t nq, int32_t k, int32_t ef, int64_t* ids, float* dists,
+                            void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ESG_H_ */

@@ -1,0 +1,399 @@
+// Host builder of the HBI-2D elastic-graph index (Section 4.2, Alg. 3).
+//
+// The segment tree over positions [0, n-1] splits node [a,b] at
+// floor((a+b)/2).  A node with b - a >= leaf owns a proximity graph; its
+// graph is a copy of its left child's graph plus the insertion of the
+// right half (Alg. 3); when the left child is a leaf its graph is first
+// built from scratch.  Every graph of one tree depth covers disjoint
+// positions, so the graphs of depth t share one adjacency array adj[t][n][R].
+//
+// Insertion follows the graph-index construction recalled in Section 2.1:
+// a beam search of width ef_construction finds candidates, edge occlusion
+// keeps at most R of them (a candidate c is dropped when an already kept
+// neighbour s is closer to c than the new point is), and reverse edges are
+// added, re-pruning a full list with the same rule.  Points are inserted in
+// batches whose size depends only on the current graph size: the searches
+// of one batch run in parallel against the graph as it was before the
+// batch, then all edge updates are applied in a fixed order.  The output is
+// therefore independent of the thread count.
+//
+// The entry point of each node graph is its medoid: the point nearest (in
+// float64) to the mean of the node's points, ties to the smaller position.
+#include <omp.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <queue>
+#include <utility>
+#include <vector>
+
+#include "../../include/esg.h"
+#include "esg_format.h"
+
+namespace {
+
+using Cand = std::pair<float, uint32_t>;  // (squared distance, position)
+
+inline float l2sq(const float* a, const float* b, int d) {
+  float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int j = 0;
+  for (; j + 8 <= d; j += 8) {
+    for (int e = 0; e < 8; e++) {
+      float t = a[j + e] - b[j + e];
+      acc[e] += t * t;
+    }
+  }
+  float s = 0.f;
+  for (; j < d; j++) {
+    float t = a[j] - b[j];
+    s += t * t;
+  }
+  return s + ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+struct VisitTags {
+  std::vector<uint32_t> tag;
+  uint32_t cur = 0;
+  void reset(int64_t n) {
+    tag.assign((size_t)n, 0);
+    cur = 0;
+  }
+  void next() {
+    if (++cur == 0) {
+      std::fill(tag.begin(), tag.end(), 0);
+      cur = 1;
+    }
+  }
+};
+
+struct Builder {
+  int64_t n;
+  int d, R, leaf, efc, batch_max, n_depth, verbose;
+  const float* X;          // [n][d], position order
+  uint32_t* adj;           // [n_depth][n][R]
+
+  uint32_t* rows(int t) { return adj + (size_t)t * (size_t)n * (size_t)R; }
+  const float* vec(uint32_t p) const { return X + (size_t)p * (size_t)d; }
+
+  static int row_len(const uint32_t* row, int R) {
+    int c = 0;
+    while (c < R && row[c] != ESG_NO_NODE) c++;
+    return c;
+  }
+
+  // Beam search over the graph `rw` (rows hold global positions) from ep.
+  void search(const uint32_t* rw, uint32_t ep, const float* q, int ef, VisitTags& vt,
+              std::vector<Cand>& out) const {
+    vt.next();
+    std::priority_queue<Cand, std::vector<Cand>, std::greater<Cand>> cand;  // min
+    std::priority_queue<Cand> res;                                          // max
+    Cand e{l2sq(vec(ep), q, d), ep};
+    vt.tag[ep] = vt.cur;
+    cand.push(e);
+    res.push(e);
+    while (!cand.empty()) {
+      Cand c = cand.top();
+      if ((int)res.size() >= ef && res.top() < c) break;
+      cand.pop();
+      const uint32_t* row = rw + (size_t)c.second * R;
+      for (int s = 0; s < R; s++) {
+        uint32_t v = row[s];
+        if (v == ESG_NO_NODE) break;
+        if (vt.tag[v] == vt.cur) continue;
+        vt.tag[v] = vt.cur;
+        Cand nv{l2sq(vec(v), q, d), v};
+        if ((int)res.size() < ef || nv < res.top()) {
+          cand.push(nv);
+          res.push(nv);
+          if ((int)res.size() > ef) res.pop();
+        }
+      }
+    }
+    out.resize(res.size());
+    for (size_t i = res.size(); i-- > 0;) {
+      out[i] = res.top();
+      res.pop();
+    }
+  }
+
+  // Edge occlusion over candidates sorted ascending by distance to the base point.
+  int occlude(const std::vector<Cand>& cands, uint32_t self, uint32_t* out) const {
+    int m = 0;
+    for (const Cand& c : cands) {
+      if (m >= R) break;
+      if (c.second == self) continue;
+      bool keep = true;
+      for (int s = 0; s < m; s++) {
+        if (l2sq(vec(c.second), vec(out[s]), d) < c.first) {
+          keep = false;
+          break;
+        }
+      }
+      if (keep) out[m++] = c.second;
+    }
+    for (int s = m; s < R; s++) out[s] = ESG_NO_NODE;
+    return m;
+  }
+
+  uint32_t medoid(int64_t a, int64_t b) const {
+    std::vector<double> mean((size_t)d, 0.0);
+    for (int64_t p = a; p <= b; p++)
+      for (int j = 0; j < d; j++) mean[j] += (double)X[(size_t)p * d + j];
+    for (int j = 0; j < d; j++) mean[j] /= (double)(b - a + 1);
+    double best = INFINITY;
+    uint32_t arg = (uint32_t)a;
+    for (int64_t p = a; p <= b; p++) {
+      double s = 0.0;
+      for (int j = 0; j < d; j++) {
+        double t = (double)X[(size_t)p * d + j] - mean[j];
+        s += t * t;
+      }
+      if (s < best) {
+        best = s;
+        arg = (uint32_t)p;
+      }
+    }
+    return arg;
+  }
+
+  // Graph on [a, s-1] (rows of `rw`) receives positions s..e.
+  void insert_range(uint32_t* rw, int64_t a, int64_t s, int64_t e, bool par) {
+    int64_t cur = s;
+    int64_t ep_size = 0;
+    uint32_t ep = (uint32_t)a;
+    std::vector<std::vector<uint32_t>> sel;
+    std::vector<std::pair<uint64_t, float>> prop;  // ((target<<32)|source, dist)
+    while (cur <= e) {
+      int64_t size = cur - a;
+      if (size >= 2 * ep_size + 1 || ep_size == 0) {
+        ep = medoid(a, cur - 1);
+        ep_size = size;
+      }
+      int64_t B = std::max<int64_t>(1, std::min<int64_t>(size / 16, batch_max));
+      B = std::min<int64_t>(B, e - cur + 1);
+      sel.assign((size_t)B, std::vector<uint32_t>((size_t)R, ESG_NO_NODE));
+      // 1) searches against the frozen graph
+#pragma omp parallel for schedule(dynamic, 1) if (par && B > 1)
+      for (int64_t i = 0; i < B; i++) {
+        std::vector<Cand> cands;
+        uint32_t p = (uint32_t)(cur + i);
+        // One visit-tag array per OS thread: omp_get_thread_num() is 0 inside
+        // the serialized inner region of every outer thread, so it cannot
+        // index per-thread state here.
+        static thread_local VisitTags vt;
+        if ((int64_t)vt.tag.size() != n) vt.reset(n);
+        search(rw, ep, vec(p), efc, vt, cands);
+        occlude(cands, p, sel[(size_t)i].data());
+      }
+      // 2) forward edges and reverse-edge proposals, in position order
+      prop.clear();
+      for (int64_t i = 0; i < B; i++) {
+        uint32_t p = (uint32_t)(cur + i);
+        std::memcpy(rw + (size_t)p * R, sel[(size_t)i].data(), sizeof(uint32_t) * R);
+        for (int j = 0; j < R; j++) {
+          uint32_t c = sel[(size_t)i][(size_t)j];
+          if (c == ESG_NO_NODE) break;
+          prop.push_back({((uint64_t)c << 32) | p, 0.f});
+        }
+      }
+      std::sort(prop.begin(), prop.end());
+      // group boundaries per target
+      std::vector<size_t> starts;
+      for (size_t i = 0; i < prop.size(); i++)
+        if (i == 0 || (prop[i].first >> 32) != (prop[i - 1].first >> 32)) starts.push_back(i);
+      starts.push_back(prop.size());
+      // 3) reverse edges, one target per iteration (targets are distinct)
+      const int64_t n_groups = (int64_t)starts.size() - 1;
+#pragma omp parallel for schedule(dynamic, 16) if (par && n_groups > 64)
+      for (int64_t g = 0; g < n_groups; g++) {
+        size_t i0 = starts[(size_t)g], i1 = starts[(size_t)g + 1];
+        uint32_t c = (uint32_t)(prop[i0].first >> 32);
+        uint32_t* row = rw + (size_t)c * R;
+        int len = row_len(row, R);
+        if (len + (int)(i1 - i0) <= R) {
+          for (size_t i = i0; i < i1; i++) row[len++] = (uint32_t)(prop[i].first & 0xFFFFFFFFu);
+          continue;
+        }
+        std::vector<Cand> cands;
+        cands.reserve((size_t)len + (i1 - i0));
+        for (int j = 0; j < len; j++) cands.push_back({l2sq(vec(c), vec(row[j]), d), row[j]});
+        for (size_t i = i0; i < i1; i++) {
+          uint32_t p = (uint32_t)(prop[i].first & 0xFFFFFFFFu);
+          cands.push_back({l2sq(vec(c), vec(p), d), p});
+        }
+        std::sort(cands.begin(), cands.end());
+        occlude(cands, c, row);
+      }
+      cur += B;
+    }
+  }
+
+  void build_node(int t, int64_t a, int64_t b, bool par) {
+    int64_t mid = (a + b) / 2;
+    uint32_t* rw = rows(t);
+    if (mid - a >= leaf) {
+      // left child owns a graph at depth t+1: copy it
+      std::memcpy(rw + (size_t)a * R, rows(t + 1) + (size_t)a * R,
+                  sizeof(uint32_t) * (size_t)R * (size_t)(mid - a + 1));
+    } else {
+      // build the left half from scratch, starting from its first point
+      for (int j = 0; j < R; j++) rw[(size_t)a * R + j] = ESG_NO_NODE;
+      if (mid > a) insert_range(rw, a, a + 1, mid, par);
+    }
+    insert_range(rw, a, mid + 1, b, par);
+  }
+};
+
+struct NodeRef {
+  int depth;
+  int64_t heap, a, b;
+};
+
+void collect(int64_t a, int64_t b, int depth, int64_t heap, int leaf, std::vector<NodeRef>& out) {
+  if (b - a < leaf) return;
+  out.push_back({depth, heap, a, b});
+  int64_t mid = (a + b) / 2;
+  collect(a, mid, depth + 1, 2 * heap, leaf, out);
+  collect(mid + 1, b, depth + 1, 2 * heap + 1, leaf, out);
+}
+
+bool write_all(FILE* f, const void* p, uint64_t bytes) {
+  const char* c = static_cast<const char*>(p);
+  while (bytes > 0) {
+    size_t chunk = (size_t)std::min<uint64_t>(bytes, 1ull << 30);
+    if (fwrite(c, 1, chunk, f) != chunk) return false;
+    c += chunk;
+    bytes -= chunk;
+  }
+  return true;
+}
+
+bool pad_to(FILE* f, uint64_t off) {
+  long pos = ftell(f);
+  if (pos < 0) return false;
+  static const char zeros[4096] = {0};
+  uint64_t cur = (uint64_t)pos;
+  while (cur < off) {
+    size_t chunk = (size_t)std::min<uint64_t>(off - cur, sizeof(zeros));
+    if (fwrite(zeros, 1, chunk, f) != chunk) return false;
+    cur += chunk;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_t n, int32_t d,
+                                   const esg_build_params* params, const char* out_path) {
+  if (!vecs || !attr || !params || !out_path || n <= 0 || n >= (int64_t)ESG_NO_NODE || d <= 0)
+    return ESG_EINVAL;
+  const esg_build_params& P = *params;
+  if (P.degree < 1 || P.degree > ESG_DEGREE_MAX || P.leaf < 1 || P.ef_construction < 1 ||
+      (P.fanout != 2 && P.fanout != 0))
+    return P.fanout != 2 && P.fanout != 0 ? ESG_EUNSUPPORTED : ESG_EINVAL;
+  for (int64_t i = 0; i < n; i++)
+    if (std::isnan(attr[i])) return ESG_EINVAL;
+  try {
+    int nthreads = P.threads > 0 ? P.threads : omp_get_max_threads();
+    omp_set_num_threads(nthreads);
+
+    // Re-rank by attribute: position p holds the p-th smallest value.
+    std::vector<int64_t> order((size_t)n);
+    for (int64_t i = 0; i < n; i++) order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t u, int64_t v) { return attr[u] < attr[v]; });
+    std::vector<double> sorted_attr((size_t)n);
+    std::vector<float> X((size_t)n * (size_t)d);
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < n; p++) {
+      sorted_attr[(size_t)p] = attr[order[(size_t)p]];
+      std::memcpy(&X[(size_t)p * d], vecs + (size_t)order[(size_t)p] * d, sizeof(float) * d);
+    }
+
+    std::vector<NodeRef> nodes;
+    collect(0, n - 1, 0, 1, P.leaf, nodes);
+    int n_depth = 0;
+    for (const NodeRef& nd : nodes) n_depth = std::max(n_depth, nd.depth + 1);
+    if (n_depth > 40) return ESG_ERANGE;
+
+    Builder B;
+    B.n = n;
+    B.d = d;
+    B.R = P.degree;
+    B.leaf = P.leaf;
+    B.efc = P.ef_construction;
+    B.batch_max = P.batch_max > 0 ? P.batch_max : 1024;
+    B.n_depth = n_depth;
+    B.verbose = P.verbose;
+    B.X = X.data();
+    std::vector<uint32_t> adj((size_t)n_depth * (size_t)n * (size_t)P.degree, ESG_NO_NODE);
+    B.adj = adj.data();
+
+    std::vector<uint32_t> ep((size_t)1 << n_depth, ESG_NO_NODE);
+    for (int t = n_depth - 1; t >= 0; t--) {
+      std::vector<NodeRef> level;
+      for (const NodeRef& nd : nodes)
+        if (nd.depth == t) level.push_back(nd);
+      bool outer = (int64_t)level.size() >= 2 * (int64_t)nthreads;
+      if (outer) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t i = 0; i < (int64_t)level.size(); i++)
+          B.build_node(t, level[(size_t)i].a, level[(size_t)i].b, false);
+      } else {
+        for (const NodeRef& nd : level) B.build_node(t, nd.a, nd.b, true);
+      }
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int64_t i = 0; i < (int64_t)level.size(); i++)
+        ep[(size_t)level[(size_t)i].heap] = B.medoid(level[(size_t)i].a, level[(size_t)i].b);
+      if (P.verbose) fprintf(stderr, "[esg_build] depth %d: %zu graph nodes\n", t, level.size());
+    }
+
+    // Write the file.
+    esg::FileHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, esg::kMagic, 8);
+    h.version = esg::kVersion;
+    h.header_bytes = esg::kHeaderBytes;
+    h.n = n;
+    h.d = d;
+    h.degree = P.degree;
+    h.leaf = P.leaf;
+    h.fanout = 2;
+    h.n_depth = n_depth;
+    h.c_den = 2;
+    h.ef_construction = P.ef_construction;
+    h.off_ids = esg::align_up(esg::kHeaderBytes);
+    h.off_attr = esg::align_up(h.off_ids + esg::bytes_ids(n));
+    h.off_vec = esg::align_up(h.off_attr + esg::bytes_attr(n));
+    h.off_adj = esg::align_up(h.off_vec + esg::bytes_vec(n, d));
+    h.off_ep = esg::align_up(h.off_adj + esg::bytes_adj(n, n_depth, P.degree));
+    h.file_bytes = h.off_ep + esg::bytes_ep(n_depth);
+    const esg::Crc32c& crc = esg::crc32c();
+    h.crc_sections[0] = crc.update(0, order.data(), esg::bytes_ids(n));
+    h.crc_sections[1] = crc.update(0, sorted_attr.data(), esg::bytes_attr(n));
+    h.crc_sections[2] = crc.update(0, X.data(), esg::bytes_vec(n, d));
+    h.crc_sections[3] = crc.update(0, adj.data(), esg::bytes_adj(n, n_depth, P.degree));
+    h.crc_sections[4] = crc.update(0, ep.data(), esg::bytes_ep(n_depth));
+    h.crc_header = crc.update(0, &h, offsetof(esg::FileHeader, crc_header));
+
+    FILE* f = fopen(out_path, "wb");
+    if (!f) return ESG_EIO;
+    bool ok = write_all(f, &h, sizeof(h)) && pad_to(f, h.off_ids) &&
+              write_all(f, order.data(), esg::bytes_ids(n)) && pad_to(f, h.off_attr) &&
+              write_all(f, sorted_attr.data(), esg::bytes_attr(n)) && pad_to(f, h.off_vec) &&
+              write_all(f, X.data(), esg::bytes_vec(n, d)) && pad_to(f, h.off_adj) &&
+              write_all(f, adj.data(), esg::bytes_adj(n, n_depth, P.degree)) &&
+              pad_to(f, h.off_ep) && write_all(f, ep.data(), esg::bytes_ep(n_depth));
+    ok = (fclose(f) == 0) && ok;
+    return ok ? ESG_OK : ESG_EIO;
+  } catch (const std::bad_alloc&) {
+    return ESG_ENOMEM;
+  } catch (...) {
+    return ESG_EINVAL;
+  }
+}

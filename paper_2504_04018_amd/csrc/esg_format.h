@@ -1,0 +1,81 @@
+// Index file layout shared by the host builder and the loader of libesg.
+// The byte layout is documented in include/esg.h (index file, version 1).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <cstring>
+
+namespace esg {
+
+constexpr char kMagic[8] = {'E', 'S', 'G', 'I', 'D', 'X', '0', '1'};
+constexpr uint32_t kVersion = 1;
+constexpr uint32_t kHeaderBytes = 512;
+constexpr uint64_t kAlign = 4096;
+
+#pragma pack(push, 1)
+struct FileHeader {
+  char magic[8];
+  uint32_t version;
+  uint32_t header_bytes;
+  int64_t n;
+  int32_t d, degree, leaf, fanout, n_depth, c_den, ef_construction, pad;
+  uint64_t off_ids, off_attr, off_vec, off_adj, off_ep, file_bytes;
+  uint32_t crc_sections[5];
+  uint32_t crc_header;  // crc32c of bytes [0, offsetof(crc_header))
+};
+#pragma pack(pop)
+static_assert(sizeof(FileHeader) == 128, "header layout");
+static_assert(offsetof(FileHeader, crc_header) == 124, "header layout");
+
+inline uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Section sizes in bytes.
+inline uint64_t bytes_ids(int64_t n) { return (uint64_t)n * 8; }
+inline uint64_t bytes_attr(int64_t n) { return (uint64_t)n * 8; }
+inline uint64_t bytes_vec(int64_t n, int32_t d) { return (uint64_t)n * (uint64_t)d * 4; }
+inline uint64_t bytes_adj(int64_t n, int32_t depth, int32_t r) {
+  return (uint64_t)depth * (uint64_t)n * (uint64_t)r * 4;
+}
+inline uint64_t bytes_ep(int32_t depth) { return ((uint64_t)1 << depth) * 4; }
+
+// Software CRC-32C (Castagnoli, reflected polynomial 0x82F63B78), eight
+// bytes per step with slicing tables.
+class Crc32c {
+ public:
+  Crc32c() {
+    for (uint32_t i = 0; i < 256; i++) {
+      uint32_t c = i;
+      for (int k = 0; k < 8; k++) c = (c >> 1) ^ ((c & 1) ? 0x82F63B78u : 0u);
+      t_[0][i] = c;
+    }
+    for (uint32_t i = 0; i < 256; i++)
+      for (int s = 1; s < 8; s++) t_[s][i] = (t_[s - 1][i] >> 8) ^ t_[0][t_[s - 1][i] & 0xFF];
+  }
+  uint32_t update(uint32_t crc, const void* data, size_t len) const {
+    const uint8_t* p = static_cast<const uint8_t*>(data);
+    crc = ~crc;
+    while (len >= 8) {
+      uint64_t w;
+      std::memcpy(&w, p, 8);
+      w ^= crc;
+      crc = t_[7][w & 0xFF] ^ t_[6][(w >> 8) & 0xFF] ^ t_[5][(w >> 16) & 0xFF] ^
+            t_[4][(w >> 24) & 0xFF] ^ t_[3][(w >> 32) & 0xFF] ^ t_[2][(w >> 40) & 0xFF] ^
+            t_[1][(w >> 48) & 0xFF] ^ t_[0][(w >> 56) & 0xFF];
+      p += 8;
+      len -= 8;
+    }
+    while (len--) crc = (crc >> 8) ^ t_[0][(crc ^ *p++) & 0xFF];
+    return ~crc;
+  }
+
+ private:
+  uint32_t t_[8][256];
+};
+
+inline const Crc32c& crc32c() {
+  static const Crc32c c;
+  return c;
+}
+
+}  // namespace esg

@@ -1,0 +1,361 @@
+// Range-filtered beam search on gfx950: one wave64 per query.
+//
+// Per query the wave
+//  1. picks at most two tree nodes with Alg. 4 (integer descent, Section 4.2),
+//  2. runs Alg. 1 under POST (Sections 2.1-2.2) on each graph node, or scans
+//     a leaf, and
+//  3. merges the two answers (Alg. 4, last step) and writes the top k.
+//
+// Data layout inside the wave:
+//  - P (candidates) and Q (results) are sorted ascending lists of 64-bit
+//    keys (float distance bits above the position), held in registers as
+//    E words per lane; element i lives in word i/64 of lane i%64.
+//  - One expansion reads a 64-byte adjacency row (16 lanes x 4 B), tests
+//    and sets the visited bits in an LDS hash (global bitmap once the hash
+//    is 3/4 full), gathers the new neighbours' vectors with 16-byte loads
+//    (G lanes per vector), reduces each distance across its G lanes, sorts
+//    the <= 16 new keys with a bitonic network and merges them into P and
+//    (the in-range ones) into Q with a bitonic merge.
+//  - Merging a whole expansion at once gives the same P, Q and visited set
+//    as inserting the neighbours one by one (Alg. 1 cuts Q back to m only
+//    after the neighbour loop; P keeps its cand_cap best).
+//
+// Distances follow one fixed float32 order: each lane owns chunks t, t+G,
+// ... of W consecutive dimensions (one 16-byte load), accumulates each
+// squared difference with one fma, then the G lanes add pairwise
+// (xor-butterfly: the adjacent-pair tree).
+#pragma once
+
+#include "esg_kernels.h"
+#include "esg_wave.h"
+
+namespace esgk {
+
+template <int KIND>
+struct Traits;
+template <>
+struct Traits<kF32> {
+  static constexpr int W = 4;
+};
+template <>
+struct Traits<kBF16> {
+  static constexpr int W = 8;
+};
+template <>
+struct Traits<kFP8> {
+  static constexpr int W = 16;
+};
+
+struct WaveLds {
+  uint64_t stage[64];
+  float fstage[64];
+  uint32_t ids[64];
+};
+static_assert(sizeof(WaveLds) == kStageBytes, "staging size");
+
+__device__ __forceinline__ uint32_t* wave_table(WaveLds* L) {
+  return reinterpret_cast<uint32_t*>(L + 1);
+}
+
+// ---- distances ------------------------------------------------------------
+
+// OCP E4M3 code to float32, exact.
+__device__ __forceinline__ float e4m3_to_f32(uint32_t c) {
+  uint32_t s = (c & 0x80u) << 24;
+  uint32_t e = (c >> 3) & 15u, m = c & 7u;
+  float v = (e == 0u) ? (float)m * 0.001953125f : __uint_as_float(((e + 120u) << 23) | (m << 20));
+  return __uint_as_float(__float_as_uint(v) | s);
+}
+
+template <int KIND>
+__device__ __forceinline__ uint4 load_chunk(const SearchArgs& A, uint32_t id, int ch) {
+  const uint4* p;
+  if constexpr (KIND == kF32)
+    p = reinterpret_cast<const uint4*>(A.vec + (size_t)id * A.dp) + ch;
+  else if constexpr (KIND == kBF16)
+    p = reinterpret_cast<const uint4*>(A.vec16 + (size_t)id * A.dp) + ch;
+  else
+    p = reinterpret_cast<const uint4*>(A.vec8 + (size_t)id * A.dp) + ch;
+  return *p;
+}
+
+__device__ __forceinline__ float sqacc(float x, float q, float acc) {
+  float delta = x - q;
+  return __builtin_fmaf(delta, delta, acc);
+}
+
+template <int KIND>
+__device__ __forceinline__ float chunk_acc(const uint4& raw, const float* qc, float scale, float acc) {
+  const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+  if constexpr (KIND == kF32) {
+#pragma unroll
+    for (int e = 0; e < 4; e++) acc = sqacc(__uint_as_float(w[e]), qc[e], acc);
+  } else if constexpr (KIND == kBF16) {
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      uint32_t h = (e & 1) ? (w[e >> 1] & 0xFFFF0000u) : (w[e >> 1] << 16);
+      acc = sqacc(__uint_as_float(h), qc[e], acc);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 16; e++) {
+      uint32_t c = (w[e >> 2] >> (8 * (e & 3))) & 0xFFu;
+      acc = sqacc(scale * e4m3_to_f32(c), qc[e], acc);
+    }
+  }
+  return acc;
+}
+
+template <int G>
+__device__ __forceinline__ float group_sum(float acc, int lane) {
+#pragma unroll
+  for (int s = 1; s < G; s <<= 1) acc = acc + xor_f(acc, s, lane);
+  return acc;
+}
+
+template <int KIND, int G, int CPL>
+__device__ __forceinline__ void load_query(const float* q, int d, int lane,
+                                           float (&qr)[CPL][Traits<KIND>::W]) {
+  constexpr int W = Traits<KIND>::W;
+  const int t = lane % G;
+#pragma unroll
+  for (int c = 0; c < CPL; c++)
+#pragma unroll
+    for (int e = 0; e < W; e++) {
+      int j = (t + c * G) * W + e;
+      qr[c][e] = j < d ? q[j] : 0.0f;
+    }
+}
+
+// Distances of up to 16 vectors whose positions sit in lanes 0..n_new-1 of
+// `nid`.  Returns lane j's distance (j < n_new).
+template <int KIND, int G, int CPL>
+__device__ __forceinline__ float batch_dist(const SearchArgs& A, uint32_t nid, int n_new,
+                                            const float (&qr)[CPL][Traits<KIND>::W], WaveLds* L,
+                                            int lane) {
+  constexpr int W = Traits<KIND>::W;
+  constexpr int VPG = (kWave / G) < kBatch ? (kWave / G) : kBatch;  // vectors per round
+  constexpr int NR = (kBatch + VPG - 1) / VPG;                       // rounds for 16
+  constexpr int RF0 = 16 / CPL;
+  constexpr int RF = RF0 < 1 ? 1 : (RF0 > NR ? NR : RF0);            // rounds in flight
+  const int grp = lane / G, t = lane % G;
+  const int C = (A.d + W - 1) / W;
+#pragma unroll
+  for (int r0 = 0; r0 < NR; r0 += RF) {
+    if (r0 * VPG >= n_new) break;
+    uint4 raw[RF][CPL];
+    float sc[RF];
+#pragma unroll
+    for (int rr = 0; rr < RF; rr++) {
+      const int slot = (r0 + rr) * VPG + grp;
+      const uint32_t id = bperm(nid, slot & 63);
+      const bool ok = grp < VPG && slot < n_new;
+#pragma unroll
+      for (int c = 0; c < CPL; c++) {
+        const int ch = t + c * G;
+        raw[rr][c] = (ok && ch < C) ? load_chunk<KIND>(A, id, ch) : make_uint4(0, 0, 0, 0);
+      }
+      if constexpr (KIND == kFP8) sc[rr] = ok ? A.scale8[id] : 0.0f;
+      else sc[rr] = 1.0f;
+    }
+#pragma unroll
+    for (int rr = 0; rr < RF; rr++) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int c = 0; c < CPL; c++) acc = chunk_acc<KIND>(raw[rr][c], qr[c], sc[rr], acc);
+      acc = group_sum<G>(acc, lane);
+      const int slot = (r0 + rr) * VPG + grp;
+      if (t == 0 && grp < VPG && slot < n_new) L->fstage[slot] = acc;
+    }
+  }
+  wave_lds_sync();
+  return lane < n_new ? L->fstage[lane] : 0.0f;
+}
+
+// ---- ordered lists ------------------------------------------------------------
+
+// Ascending sort of the 16 keys in lanes 0..15 (bitonic network).
+__device__ __forceinline__ uint64_t sort16(uint64_t v, int lane) {
+#pragma unroll
+  for (int k = 2; k <= 16; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j >= 1; j >>= 1) {
+      uint64_t p = xor64(v, j, lane);
+      bool up = (lane & k) == 0;
+      bool lower = (lane & j) == 0;
+      v = (lower == up) ? kmin(v, p) : kmax(v, p);
+    }
+  }
+  return v;
+}
+
+// Sorts a bitonic list of 64*E keys ascending, then drops elements >= cap.
+template <int E>
+__device__ __forceinline__ void bitonic_finish(uint64_t (&L)[E], int cap, int lane) {
+#pragma unroll
+  for (int s = E / 2; s >= 1; s >>= 1) {
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      if ((e & s) == 0) {
+        uint64_t lo = kmin(L[e], L[e + s]), hi = kmax(L[e], L[e + s]);
+        L[e] = lo;
+        L[e + s] = hi;
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) {
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      uint64_t p = xor64(L[e], s, lane);
+      L[e] = (lane & s) ? kmax(L[e], p) : kmin(L[e], p);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; e++)
+    if (e * kWave + lane >= cap) L[e] = kKeyInf;
+}
+
+// Merges 16 sorted keys into the sorted list; `brev` holds them reversed in
+// lanes 48..63 (lane 63-j = j-th smallest) and +inf elsewhere.
+template <int E>
+__device__ __forceinline__ void list_merge16(uint64_t (&L)[E], uint64_t brev, int cap, int lane) {
+  L[E - 1] = kmin(L[E - 1], brev);
+  bitonic_finish<E>(L, cap, lane);
+}
+
+// Merges two sorted lists of the same shape into the first.
+template <int E>
+__device__ __forceinline__ void list_merge(uint64_t (&A)[E], const uint64_t (&B)[E], int cap,
+                                           int lane) {
+#pragma unroll
+  for (int e = 0; e < E; e++) A[e] = kmin(A[e], bperm64(B[E - 1 - e], 63 - lane));
+  bitonic_finish<E>(A, cap, lane);
+}
+
+// Removes element 0.
+template <int E>
+__device__ __forceinline__ void list_pop(uint64_t (&L)[E], int lane) {
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    uint64_t nxt = (e + 1 < E) ? readlane64(L[e + 1 < E ? e + 1 : e], 0) : kKeyInf;
+    uint64_t sh = bperm64(L[e], (lane + 1) & 63);
+    L[e] = lane == 63 ? nxt : sh;
+  }
+}
+
+template <int E>
+__device__ __forceinline__ uint64_t list_at(const uint64_t (&L)[E], int i) {
+  uint64_t v = kKeyInf;
+#pragma unroll
+  for (int e = 0; e < E; e++)
+    if (e == i / kWave) v = readlane64(L[e], i % kWave);
+  return v;
+}
+
+template <int E>
+__device__ __forceinline__ void list_clear(uint64_t (&L)[E]) {
+#pragma unroll
+  for (int e = 0; e < E; e++) L[e] = kKeyInf;
+}
+
+// ---- visited set ------------------------------------------------------------
+
+struct Visited {
+  uint32_t* table;
+  uint32_t* bm;    // spill bitmap of this wave slot, indexed by position - a
+  uint32_t a;
+  int inserted;    // keys held by the LDS table
+  bool spill;
+};
+
+// Test-and-set of v (lanes with `active`).  True when v was not visited.
+__device__ __forceinline__ bool visit(const SearchArgs& A, Visited& V, uint32_t v, bool active) {
+  if (!active) return false;
+  const uint32_t mask = (uint32_t)A.hash_cap - 1u;
+  uint32_t h = (v * 0x9E3779B1u) >> A.hash_shift;
+  if (!V.spill) {
+    for (;;) {
+      uint32_t old = atomicCAS(&V.table[h], kNoNode, v);
+      if (old == kNoNode) return true;
+      if (old == v) return false;
+      h = (h + 1u) & mask;
+    }
+  }
+  for (;;) {
+    uint32_t cur = V.table[h];
+    if (cur == v) return false;
+    if (cur == kNoNode) break;
+    h = (h + 1u) & mask;
+  }
+  uint32_t off = v - V.a;
+  uint32_t bit = 1u << (off & 31u);
+  uint32_t old = atomicOr(&V.bm[off >> 5], bit);
+  return (old & bit) == 0u;
+}
+
+__device__ __forceinline__ void visited_reset(const SearchArgs& A, Visited& V, int lane) {
+  for (int i = lane; i < A.hash_cap; i += kWave) V.table[i] = kNoNode;
+  V.inserted = 0;
+  V.spill = false;
+  wave_lds_sync();
+}
+
+// Switch to the global bitmap for node [a,b] before the LDS table overflows.
+__device__ __forceinline__ void visited_spill(Visited& V, uint32_t b, int lane) {
+  const uint32_t words = ((b - V.a) >> 5) + 1u;
+  for (uint32_t i = (uint32_t)lane; i < words; i += kWave) V.bm[i] = 0u;
+  __threadfence();
+  V.spill = true;
+}
+
+// ---- parts ----------------------------------------------------------------------
+
+struct Part {
+  int32_t kind;  // 1 graph, 2 scan
+  int32_t depth;
+  int64_t heap;
+  uint32_t a, b, x, y;
+};
+
+// Alg. 4: at most two parts for fanout 2 (Lemma 4.2).  Returns the count,
+// or -1 if the descent would emit more (never for a fanout-2 tree).
+__device__ __forceinline__ int select_parts(int64_t n, int64_t leaf, int32_t c_den, int64_t lq,
+                                            int64_t rq, Part (&out)[2]) {
+  struct Item {
+    int64_t a, b, x, y, heap;
+    int32_t depth;
+  };
+  Item stack[4];
+  int sp = 0, np = 0;
+  stack[sp++] = {0, n - 1, lq, rq, 1, 0};
+  while (sp > 0) {
+    Item it = stack[--sp];
+    for (;;) {
+      bool is_leaf = it.b - it.a < leaf;
+      bool elastic = !is_leaf && (int64_t)c_den * (it.y - it.x + 1) >= (it.b - it.a + 1);
+      if (is_leaf || elastic) {
+        if (np >= 2) return -1;
+        out[np++] = {is_leaf ? 2 : 1, it.depth, it.heap, (uint32_t)it.a, (uint32_t)it.b,
+                     (uint32_t)it.x, (uint32_t)it.y};
+        break;
+      }
+      int64_t mid = (it.a + it.b) / 2;
+      bool go_left = it.x <= mid, go_right = it.y > mid;
+      Item right = {mid + 1, it.b, it.x > mid + 1 ? it.x : mid + 1, it.y, 2 * it.heap + 1,
+                    it.depth + 1};
+      if (go_left) {
+        if (go_right) {
+          if (sp >= 4) return -1;
+          stack[sp++] = right;
+        }
+        it = {it.a, mid, it.x, it.y < mid ? it.y : mid, 2 * it.heap, it.depth + 1};
+      } else {
+        it = right;
+      }
+    }
+  }
+  return np;
+}
+
+}  // namespace esgk

@@ -1,0 +1,52 @@
+// Instantiates the search kernels for one vector dimension (-DESG_DIM=d).
+#include "esg_dispatch.h"
+#include "esg_search_kernel.h"
+
+#ifndef ESG_DIM
+#error "compile with -DESG_DIM=<dimension>"
+#endif
+
+namespace esgk {
+namespace {
+
+constexpr int lanes_for(int chunks) {
+  int g = 1;
+  while (g < chunks) g *= 2;
+  return g > 64 ? 64 : g;
+}
+
+template <int KIND>
+struct Shape {
+  static constexpr int C = (ESG_DIM + Traits<KIND>::W - 1) / Traits<KIND>::W;
+  static constexpr int G = lanes_for(C);
+  static constexpr int CPL = (C + G - 1) / G;
+};
+
+template <int KIND, int E>
+const void* kernel_ptr() {
+  using S = Shape<KIND>;
+  using S32 = Shape<kF32>;
+  return reinterpret_cast<const void*>(&search_kernel<KIND, S::G, S::CPL, S32::G, S32::CPL, E>);
+}
+
+template <int KIND>
+void fill(KernelTable* t) {
+  t->fn[KIND][0] = kernel_ptr<KIND, 1>();
+  t->fn[KIND][1] = kernel_ptr<KIND, 2>();
+  t->fn[KIND][2] = kernel_ptr<KIND, 4>();
+  t->fn[KIND][3] = kernel_ptr<KIND, 8>();
+  t->fn[KIND][4] = kernel_ptr<KIND, 16>();
+}
+
+}  // namespace
+}  // namespace esgk
+
+#define ESG_CAT2(a, b) a##b
+#define ESG_CAT(a, b) ESG_CAT2(a, b)
+
+extern "C" void ESG_CAT(esg_register_dim_, ESG_DIM)(esgk::KernelTable* t) {
+  t->dim = ESG_DIM;
+  esgk::fill<esgk::kF32>(t);
+  esgk::fill<esgk::kBF16>(t);
+  esgk::fill<esgk::kFP8>(t);
+}

@@ -1,0 +1,223 @@
+// The persistent search kernel (see esg_search_impl.h for the data layout).
+#pragma once
+
+#include "esg_search_impl.h"
+
+namespace esgk {
+
+struct PartStats {
+  int64_t hops;
+  int64_t n_visited;
+};
+
+// Alg. 1 with POST on graph node [a,b] of tree depth `depth`; results (the
+// final Q, at most m keys) are left in Q.
+template <int KIND, int G, int CPL, int E>
+__device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* Ls, Visited& V,
+                                                  const Part& pt, int m, int cap_p,
+                                                  const float (&qr)[CPL][Traits<KIND>::W],
+                                                  uint64_t (&Q)[E], uint32_t* dump, int lane) {
+  uint64_t P[E];
+  list_clear(P);
+  list_clear(Q);
+  V.a = pt.a;
+  visited_reset(A, V, lane);
+  const uint32_t* rows = A.adj + (size_t)pt.depth * (size_t)A.n * (size_t)A.R;
+  const uint32_t ep = A.ep[pt.heap];
+
+  // P <- ep ; Q <- ep when ep is in range (POST)
+  visit(A, V, ep, lane == 0);
+  V.inserted = 1;
+  float dep = batch_dist<KIND, G, CPL>(A, ep, 1, qr, Ls, lane);
+  const uint64_t kep = make_key(__uint_as_float(readlane(__float_as_uint(dep), 0)), ep);
+  if (lane == 0) {
+    P[0] = kep;
+    if (ep >= pt.x && ep <= pt.y) Q[0] = kep;
+  }
+  if (dump && lane == 0 && A.visited_cap > 0) dump[0] = ep;
+  int64_t nvis = 1, hops = 0;
+
+  for (;;) {
+    const uint64_t u = readlane64(P[0], 0);
+    if (u == kKeyInf) break;                                   // P is empty
+    const uint64_t worst = list_at(Q, m - 1);
+    if (worst != kKeyInf && worst < u) break;                  // farther than a full Q
+    if (A.hop_budget >= 0 && hops >= A.hop_budget) break;
+    list_pop(P, lane);
+    hops++;
+
+    const uint32_t upos = key_pos(u);
+    uint32_t v = lane < A.R ? rows[(size_t)upos * A.R + lane] : kNoNode;
+    if (!V.spill && V.inserted + kBatch > A.hash_limit) visited_spill(V, pt.b, lane);
+    const bool is_new = visit(A, V, v, v != kNoNode && v >= pt.a && v <= pt.b);
+    const uint64_t nm = ballot(is_new);
+    const int n_new = __popcll(nm);
+    if (!V.spill) V.inserted += n_new;
+    if (n_new == 0) continue;
+    if (is_new) Ls->ids[rank_below(nm)] = v;
+    wave_lds_sync();
+    const uint32_t nid = lane < n_new ? Ls->ids[lane] : kNoNode;
+    if (dump && lane < n_new && nvis + lane < A.visited_cap) dump[nvis + lane] = nid;
+    nvis += n_new;
+
+    const float bd = batch_dist<KIND, G, CPL>(A, nid, n_new, qr, Ls, lane);
+    uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
+    key = sort16(key, lane);
+    // A batch whose best key loses to a full Q can change neither list.
+    const uint64_t kmin0 = readlane64(key, 0);
+    if (worst != kKeyInf && worst < kmin0) continue;
+    list_merge16(P, bperm64(key, 63 - lane), cap_p, lane);
+    const uint32_t kp = key_pos(key);
+    const bool inr = lane < kBatch && key != kKeyInf && kp >= pt.x && kp <= pt.y;
+    const uint64_t qm = ballot(inr);
+    if (qm != 0) {
+      Ls->stage[lane] = kKeyInf;
+      wave_lds_sync();
+      if (inr) Ls->stage[63 - rank_below(qm)] = key;
+      wave_lds_sync();
+      list_merge16(Q, Ls->stage[lane], m, lane);
+    }
+  }
+  return {hops, nvis};
+}
+
+// Scores positions [x,y] (a leaf) with float32 distances; keeps the best k.
+template <int G32, int CPL32, int E>
+__device__ __forceinline__ void scan_leaf(const SearchArgs& A, WaveLds* Ls, const Part& pt, int k,
+                                          const float (&qr32)[CPL32][4], uint64_t (&R)[E],
+                                          int lane) {
+  list_clear(R);
+  for (uint32_t base = pt.x; base <= pt.y; base += kBatch) {
+    const int n_new = (int)((pt.y - base + 1) < (uint32_t)kBatch ? (pt.y - base + 1) : kBatch);
+    const uint32_t nid = lane < n_new ? base + (uint32_t)lane : kNoNode;
+    const float bd = batch_dist<kF32, G32, CPL32>(A, nid, n_new, qr32, Ls, lane);
+    uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
+    key = sort16(key, lane);
+    list_merge16(R, bperm64(key, 63 - lane), k, lane);
+    if (base > 0xFFFFFFFFu - kBatch) break;
+  }
+}
+
+// Recomputes every key of Q with float32 distances and keeps the best k.
+template <int G32, int CPL32, int E>
+__device__ __forceinline__ void rerank_f32(const SearchArgs& A, WaveLds* Ls, int k,
+                                           const float (&qr32)[CPL32][4], uint64_t (&Q)[E],
+                                           int lane) {
+  uint64_t R[E];
+  list_clear(R);
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+#pragma unroll
+    for (int s = 0; s < kWave / kBatch; s++) {
+      const uint64_t kq = bperm64(Q[e], (s * kBatch + lane) & 63);
+      const bool ok = lane < kBatch && kq != kKeyInf;
+      const int n_new = __popcll(ballot(ok));
+      if (n_new == 0) continue;
+      const uint32_t nid = ok ? key_pos(kq) : kNoNode;
+      const float bd = batch_dist<kF32, G32, CPL32>(A, nid, n_new, qr32, Ls, lane);
+      uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
+      key = sort16(key, lane);
+      list_merge16(R, bperm64(key, 63 - lane), k, lane);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; e++) Q[e] = R[e];
+}
+
+template <int KIND, int G, int CPL, int G32, int CPL32, int E>
+__device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, Visited& V,
+                                              int64_t qi, int lane) {
+  const int k = A.k;
+  int64_t* ids = A.ids + qi * k;
+  float* dists = A.dists + qi * k;
+  const int64_t lq = A.l[qi], rq = A.r[qi];
+  Part parts[2];
+  int np = 0;
+  const bool valid = lq >= 0 && rq < A.n && lq <= rq;
+  if (valid) np = select_parts(A.n, A.leaf, A.c_den, lq, rq, parts);
+  if (!valid || np < 0) {
+    for (int i = lane; i < k; i += kWave) {
+      ids[i] = -1;
+      dists[i] = __int_as_float(0x7F800000);
+    }
+    if (lane == 0 && A.n_invalid) atomicAdd((unsigned long long*)A.n_invalid, 1ull);
+    if (A.trace && lane < 2) A.trace[qi * 2 + lane].kind = 0;
+    return;
+  }
+
+  const float* q = A.queries + qi * (int64_t)A.d;
+  float qr[CPL][Traits<KIND>::W];
+  load_query<KIND, G, CPL>(q, A.d, lane, qr);
+  float qr32[CPL32][4];
+  if constexpr (KIND != kF32) load_query<kF32, G32, CPL32>(q, A.d, lane, qr32);
+
+  const int m = A.ef;
+  const int cap_p = A.cand_cap;
+  uint64_t Res[E];
+  list_clear(Res);
+  for (int p = 0; p < np; p++) {
+    const Part pt = parts[p];
+    uint64_t Qp[E];
+    PartStats st{0, 0};
+    if (pt.kind == 2) {
+      if constexpr (KIND == kF32) scan_leaf<G, CPL, E>(A, Ls, pt, k, qr, Qp, lane);
+      else scan_leaf<G32, CPL32, E>(A, Ls, pt, k, qr32, Qp, lane);
+      st.n_visited = (int64_t)(pt.y - pt.x) + 1;
+    } else {
+      uint32_t* dump = A.visited ? A.visited + (qi * 2 + p) * A.visited_cap : nullptr;
+      st = search_graph<KIND, G, CPL, E>(A, Ls, V, pt, m, cap_p, qr, Qp, dump, lane);
+      if constexpr (KIND != kF32)
+        if (A.rerank) rerank_f32<G32, CPL32, E>(A, Ls, k, qr32, Qp, lane);
+#pragma unroll
+      for (int e = 0; e < E; e++)
+        if (e * kWave + lane >= k) Qp[e] = kKeyInf;
+    }
+    list_merge(Res, Qp, k, lane);
+    if (A.trace && lane == 0) {
+      esg_part_trace& tr = A.trace[qi * 2 + p];
+      tr.kind = pt.kind;
+      tr.depth = pt.depth;
+      tr.heap = pt.heap;
+      tr.a = pt.a;
+      tr.b = pt.b;
+      tr.x = pt.x;
+      tr.y = pt.y;
+      tr.hops = st.hops;
+      tr.n_visited = st.n_visited;
+    }
+  }
+  if (A.trace && lane == 0 && np < 2) A.trace[qi * 2 + 1].kind = 0;
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    const int i = e * kWave + lane;
+    if (i < k) {
+      const uint64_t key = Res[e];
+      ids[i] = key == kKeyInf ? -1 : A.ext_id[key_pos(key)];
+      dists[i] = key == kKeyInf ? __int_as_float(0x7F800000) : key_dist(key);
+    }
+  }
+}
+
+template <int KIND, int G, int CPL, int G32, int CPL32, int E>
+__global__ __launch_bounds__(256) void search_kernel(SearchArgs A) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int lane = lane_id();
+  const int wid = (int)(threadIdx.x >> 6);
+  WaveLds* Ls = reinterpret_cast<WaveLds*>(smem + (size_t)wid * (kStageBytes + 4 * A.hash_cap));
+  const int64_t slot = (int64_t)blockIdx.x * kWavesPerGroup + wid;
+  Visited V;
+  V.table = wave_table(Ls);
+  V.bm = A.spill + slot * A.spill_words;
+  V.a = 0;
+  V.inserted = 0;
+  V.spill = false;
+  for (;;) {
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(A.counter, 1u);
+    const int64_t qi = (int64_t)readlane(t, 0);
+    if (qi >= A.nq) break;
+    process_query<KIND, G, CPL, G32, CPL32, E>(A, Ls, V, qi, lane);
+  }
+}
+
+}  // namespace esgk
