@@ -47,6 +47,8 @@ def parse():
                     help="queries timed on the CPU oracle (bounded sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="f32,bf16")
+    ap.add_argument("--mode", default=None, help="fixed operating point: skip the sweep")
+    ap.add_argument("--ef", type=int, default=None, help="fixed operating point: skip the sweep")
     return ap.parse_args()
 
 
@@ -133,7 +135,7 @@ def main():
     log(f"workload {w['name']} n={n} d={d} nq={nq} generated in {time.time() - t0:.1f}s")
     os.makedirs(args.cache_dir, exist_ok=True)
     tag = synth.sha256_of(w["X"][:1000], w["attr"][:1000])[:12]
-    path = os.path.join(args.cache_dir, f"sift_{n}_{tag}.esgi")
+    path = os.path.join(args.cache_dir, f"sift_{n}_R{w['degree']}_{tag}.esgi")
     if not os.path.exists(path):
         t0 = time.time()
         esg.build_index(w["X"], w["attr"].astype(np.float64), path + ".tmp", degree=w["degree"],
@@ -176,14 +178,15 @@ def main():
         return (time.perf_counter() - s) / reps
 
     sweep = []
-    for mode in args.modes.split(","):
-        for ef in EF_GRID:
+    fixed = args.mode is not None and args.ef is not None
+    for mode in ([args.mode] if fixed else args.modes.split(",")):
+        for ef in ([args.ef] if fixed else EF_GRID):
             if ef < k:
                 continue
             run(mode, ef)
             torch.cuda.synchronize()
             rec = recall_at_k(ids.cpu().numpy(), pos_of, X_pos, Q, l, r, dk, k)
-            sec = time_it(mode, ef, 3)
+            sec = time_it(mode, ef, 1 if fixed else 3)
             sweep.append(dict(mode=mode, ef=ef, recall=round(rec, 5), qps=round(nq / sec, 1)))
             log(f"sweep {mode} ef={ef} recall={rec:.4f} qps={nq / sec:,.0f}")
             if rec >= 0.995:

@@ -8,7 +8,7 @@
 namespace esgk {
 
 constexpr int kWavesPerGroup = 4;   // independent waves per workgroup
-constexpr int kBatch = 16;          // adjacency slots handled per expansion
+constexpr int kBatch = 32;          // adjacency slots handled per expansion (max degree)
 constexpr int kStageBytes = 1024;   // per-wave LDS staging ahead of the hash
 
 enum DistKind : int { kF32 = 0, kBF16 = 1, kFP8 = 2 };

@@ -127,7 +127,7 @@ __device__ __forceinline__ void load_query(const float* q, int d, int lane,
     }
 }
 
-// Distances of up to 16 vectors whose positions sit in lanes 0..n_new-1 of
+// Distances of up to 32 vectors whose positions sit in lanes 0..n_new-1 of
 // `nid`.  Returns lane j's distance (j < n_new).
 template <int KIND, int G, int CPL>
 __device__ __forceinline__ float batch_dist(const SearchArgs& A, uint32_t nid, int n_new,
@@ -135,8 +135,8 @@ __device__ __forceinline__ float batch_dist(const SearchArgs& A, uint32_t nid, i
                                             int lane) {
   constexpr int W = Traits<KIND>::W;
   constexpr int VPG = (kWave / G) < kBatch ? (kWave / G) : kBatch;  // vectors per round
-  constexpr int NR = (kBatch + VPG - 1) / VPG;                       // rounds for 16
-  constexpr int RF0 = 16 / CPL;
+  constexpr int NR = (kBatch + VPG - 1) / VPG;                       // rounds for a full batch
+  constexpr int RF0 = 8 / CPL;
   constexpr int RF = RF0 < 1 ? 1 : (RF0 > NR ? NR : RF0);            // rounds in flight
   const int grp = lane / G, t = lane % G;
   const int C = (A.d + W - 1) / W;
@@ -174,10 +174,10 @@ __device__ __forceinline__ float batch_dist(const SearchArgs& A, uint32_t nid, i
 
 // ---- ordered lists ------------------------------------------------------------
 
-// Ascending sort of the 16 keys in lanes 0..15 (bitonic network).
-__device__ __forceinline__ uint64_t sort16(uint64_t v, int lane) {
+// Ascending sort of the 32 keys in lanes 0..31 (bitonic network).
+__device__ __forceinline__ uint64_t sort32(uint64_t v, int lane) {
 #pragma unroll
-  for (int k = 2; k <= 16; k <<= 1) {
+  for (int k = 2; k <= 32; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j >= 1; j >>= 1) {
       uint64_t p = xor64(v, j, lane);
@@ -216,10 +216,10 @@ __device__ __forceinline__ void bitonic_finish(uint64_t (&L)[E], int cap, int la
     if (e * kWave + lane >= cap) L[e] = kKeyInf;
 }
 
-// Merges 16 sorted keys into the sorted list; `brev` holds them reversed in
-// lanes 48..63 (lane 63-j = j-th smallest) and +inf elsewhere.
+// Merges up to 32 sorted keys into the sorted list; `brev` holds them
+// reversed in lanes 32..63 (lane 63-j = j-th smallest) and +inf elsewhere.
 template <int E>
-__device__ __forceinline__ void list_merge16(uint64_t (&L)[E], uint64_t brev, int cap, int lane) {
+__device__ __forceinline__ void list_merge32(uint64_t (&L)[E], uint64_t brev, int cap, int lane) {
   L[E - 1] = kmin(L[E - 1], brev);
   bitonic_finish<E>(L, cap, lane);
 }
@@ -239,7 +239,7 @@ __device__ __forceinline__ void list_pop(uint64_t (&L)[E], int lane) {
 #pragma unroll
   for (int e = 0; e < E; e++) {
     uint64_t nxt = (e + 1 < E) ? readlane64(L[e + 1 < E ? e + 1 : e], 0) : kKeyInf;
-    uint64_t sh = bperm64(L[e], (lane + 1) & 63);
+    uint64_t sh = next_lane64(L[e]);
     L[e] = lane == 63 ? nxt : sh;
   }
 }
@@ -318,44 +318,58 @@ struct Part {
   uint32_t a, b, x, y;
 };
 
+// One descent of Alg. 4 from node (a,b) with part (x,y): follows the single
+// child that holds the part until a leaf or an elastic node is reached, or
+// (when allow_split) until the part straddles a split point, in which case
+// the two halves are returned in `left`/`right` and false is returned.
+struct Desc {
+  int64_t a, b, x, y, heap;
+  int32_t depth;
+};
+
+__device__ __forceinline__ bool descend(Desc& it, int64_t leaf, int32_t c_den, bool allow_split,
+                                        Desc& right, bool& split) {
+  split = false;
+  for (int guard = 0; guard < 64; guard++) {
+    const bool is_leaf = it.b - it.a < leaf;
+    const bool elastic = !is_leaf && (int64_t)c_den * (it.y - it.x + 1) >= (it.b - it.a + 1);
+    if (is_leaf || elastic) return true;
+    const int64_t mid = (it.a + it.b) / 2;
+    const bool go_left = it.x <= mid, go_right = it.y > mid;
+    if (go_left && go_right) {
+      if (!allow_split) return false;
+      right = {mid + 1, it.b, mid + 1, it.y, 2 * it.heap + 1, it.depth + 1};
+      it = {it.a, mid, it.x, mid, 2 * it.heap, it.depth + 1};
+      split = true;
+      return true;
+    }
+    if (go_left) it = {it.a, mid, it.x, it.y, 2 * it.heap, it.depth + 1};
+    else it = {mid + 1, it.b, it.x, it.y, 2 * it.heap + 1, it.depth + 1};
+  }
+  return false;
+}
+
+__device__ __forceinline__ Part to_part(const Desc& it, int64_t leaf) {
+  return {it.b - it.a < leaf ? 2 : 1, it.depth, it.heap, (uint32_t)it.a, (uint32_t)it.b,
+          (uint32_t)it.x, (uint32_t)it.y};
+}
+
 // Alg. 4: at most two parts for fanout 2 (Lemma 4.2).  Returns the count,
 // or -1 if the descent would emit more (never for a fanout-2 tree).
 __device__ __forceinline__ int select_parts(int64_t n, int64_t leaf, int32_t c_den, int64_t lq,
-                                            int64_t rq, Part (&out)[2]) {
-  struct Item {
-    int64_t a, b, x, y, heap;
-    int32_t depth;
-  };
-  Item stack[4];
-  int sp = 0, np = 0;
-  stack[sp++] = {0, n - 1, lq, rq, 1, 0};
-  while (sp > 0) {
-    Item it = stack[--sp];
-    for (;;) {
-      bool is_leaf = it.b - it.a < leaf;
-      bool elastic = !is_leaf && (int64_t)c_den * (it.y - it.x + 1) >= (it.b - it.a + 1);
-      if (is_leaf || elastic) {
-        if (np >= 2) return -1;
-        out[np++] = {is_leaf ? 2 : 1, it.depth, it.heap, (uint32_t)it.a, (uint32_t)it.b,
-                     (uint32_t)it.x, (uint32_t)it.y};
-        break;
-      }
-      int64_t mid = (it.a + it.b) / 2;
-      bool go_left = it.x <= mid, go_right = it.y > mid;
-      Item right = {mid + 1, it.b, it.x > mid + 1 ? it.x : mid + 1, it.y, 2 * it.heap + 1,
-                    it.depth + 1};
-      if (go_left) {
-        if (go_right) {
-          if (sp >= 4) return -1;
-          stack[sp++] = right;
-        }
-        it = {it.a, mid, it.x, it.y < mid ? it.y : mid, 2 * it.heap, it.depth + 1};
-      } else {
-        it = right;
-      }
-    }
+                                            int64_t rq, Part& p0, Part& p1) {
+  Desc it = {0, n - 1, lq, rq, 1, 0}, right = it, dummy = it;
+  bool split = false, s2 = false;
+  if (!descend(it, leaf, c_den, true, right, split)) return -1;
+  if (!split) {
+    p0 = to_part(it, leaf);
+    return 1;
   }
-  return np;
+  if (!descend(it, leaf, c_den, false, dummy, s2)) return -1;
+  if (!descend(right, leaf, c_den, false, dummy, s2)) return -1;
+  p0 = to_part(it, leaf);
+  p1 = to_part(right, leaf);
+  return 2;
 }
 
 }  // namespace esgk

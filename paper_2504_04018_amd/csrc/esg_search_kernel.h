@@ -37,8 +37,12 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
   if (dump && lane == 0 && A.visited_cap > 0) dump[0] = ep;
   int64_t nvis = 1, hops = 0;
 
+  // The row of the next candidate is fetched as soon as that candidate is
+  // known (right after the new batch is sorted), so the load overlaps the
+  // merges of the current expansion.
+  uint64_t u = readlane64(P[0], 0);
+  uint32_t vrow = lane < A.R ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
   for (;;) {
-    const uint64_t u = readlane64(P[0], 0);
     if (u == kKeyInf) break;                                   // P is empty
     const uint64_t worst = list_at(Q, m - 1);
     if (worst != kKeyInf && worst < u) break;                  // farther than a full Q
@@ -46,14 +50,17 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
     list_pop(P, lane);
     hops++;
 
-    const uint32_t upos = key_pos(u);
-    uint32_t v = lane < A.R ? rows[(size_t)upos * A.R + lane] : kNoNode;
+    const uint32_t v = vrow;
     if (!V.spill && V.inserted + kBatch > A.hash_limit) visited_spill(V, pt.b, lane);
     const bool is_new = visit(A, V, v, v != kNoNode && v >= pt.a && v <= pt.b);
     const uint64_t nm = ballot(is_new);
     const int n_new = __popcll(nm);
     if (!V.spill) V.inserted += n_new;
-    if (n_new == 0) continue;
+    if (n_new == 0) {
+      u = readlane64(P[0], 0);
+      vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
+      continue;
+    }
     if (is_new) Ls->ids[rank_below(nm)] = v;
     wave_lds_sync();
     const uint32_t nid = lane < n_new ? Ls->ids[lane] : kNoNode;
@@ -62,11 +69,15 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
 
     const float bd = batch_dist<KIND, G, CPL>(A, nid, n_new, qr, Ls, lane);
     uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
-    key = sort16(key, lane);
+    key = sort32(key, lane);
     // A batch whose best key loses to a full Q can change neither list.
     const uint64_t kmin0 = readlane64(key, 0);
-    if (worst != kKeyInf && worst < kmin0) continue;
-    list_merge16(P, bperm64(key, 63 - lane), cap_p, lane);
+    const bool pruned = worst != kKeyInf && worst < kmin0;
+    const uint64_t p0 = readlane64(P[0], 0);
+    u = pruned ? p0 : kmin(p0, kmin0);                         // min of P after the merge
+    vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
+    if (pruned) continue;
+    list_merge32(P, bperm64(key, 63 - lane), cap_p, lane);
     const uint32_t kp = key_pos(key);
     const bool inr = lane < kBatch && key != kKeyInf && kp >= pt.x && kp <= pt.y;
     const uint64_t qm = ballot(inr);
@@ -75,7 +86,7 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
       wave_lds_sync();
       if (inr) Ls->stage[63 - rank_below(qm)] = key;
       wave_lds_sync();
-      list_merge16(Q, Ls->stage[lane], m, lane);
+      list_merge32(Q, Ls->stage[lane], m, lane);
     }
   }
   return {hops, nvis};
@@ -92,8 +103,8 @@ __device__ __forceinline__ void scan_leaf(const SearchArgs& A, WaveLds* Ls, cons
     const uint32_t nid = lane < n_new ? base + (uint32_t)lane : kNoNode;
     const float bd = batch_dist<kF32, G32, CPL32>(A, nid, n_new, qr32, Ls, lane);
     uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
-    key = sort16(key, lane);
-    list_merge16(R, bperm64(key, 63 - lane), k, lane);
+    key = sort32(key, lane);
+    list_merge32(R, bperm64(key, 63 - lane), k, lane);
     if (base > 0xFFFFFFFFu - kBatch) break;
   }
 }
@@ -109,15 +120,15 @@ __device__ __forceinline__ void rerank_f32(const SearchArgs& A, WaveLds* Ls, int
   for (int e = 0; e < E; e++) {
 #pragma unroll
     for (int s = 0; s < kWave / kBatch; s++) {
-      const uint64_t kq = bperm64(Q[e], (s * kBatch + lane) & 63);
+      const uint64_t kq = bperm64(Q[e], (s * kBatch + lane) & 63);  // lanes < 32: block s
       const bool ok = lane < kBatch && kq != kKeyInf;
       const int n_new = __popcll(ballot(ok));
       if (n_new == 0) continue;
       const uint32_t nid = ok ? key_pos(kq) : kNoNode;
       const float bd = batch_dist<kF32, G32, CPL32>(A, nid, n_new, qr32, Ls, lane);
       uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
-      key = sort16(key, lane);
-      list_merge16(R, bperm64(key, 63 - lane), k, lane);
+      key = sort32(key, lane);
+      list_merge32(R, bperm64(key, 63 - lane), k, lane);
     }
   }
 #pragma unroll
@@ -134,7 +145,7 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
   Part parts[2];
   int np = 0;
   const bool valid = lq >= 0 && rq < A.n && lq <= rq;
-  if (valid) np = select_parts(A.n, A.leaf, A.c_den, lq, rq, parts);
+  if (valid) np = select_parts(A.n, A.leaf, A.c_den, lq, rq, parts[0], parts[1]);
   if (!valid || np < 0) {
     for (int i = lane; i < k; i += kWave) {
       ids[i] = -1;
@@ -155,7 +166,9 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
   const int cap_p = A.cand_cap;
   uint64_t Res[E];
   list_clear(Res);
-  for (int p = 0; p < np; p++) {
+#pragma unroll
+  for (int p = 0; p < 2; p++) {
+    if (p >= np) break;
     const Part pt = parts[p];
     uint64_t Qp[E];
     PartStats st{0, 0};

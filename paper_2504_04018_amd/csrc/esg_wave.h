@@ -58,11 +58,50 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Float partner value of lane ^ m (m < 64).
-__device__ __forceinline__ float xor_f(float v, int m, int lane) { return bperm_f(v, lane ^ m); }
+// Value held by lane ^ m (m a power of two below 64, a compile-time
+// constant after unrolling).  Xor 1 and 2 are DPP quad permutes, 4 and 8
+// DPP row shifts (lanes with the bit clear read lane+m, the others
+// lane-m), 16 a ds_swizzle inside each half wave, 32 a permlane32 swap.
+__device__ __forceinline__ uint32_t xor_u32(uint32_t v, int m, int lane) {
+  switch (m) {
+    case 1:
+      return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+    case 2:
+      return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+    case 4: {
+      uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x104, 0xF, 0xF, false);
+      uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x114, 0xF, 0xF, false);
+      return (lane & 4) ? dn : up;
+    }
+    case 8: {
+      uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x108, 0xF, 0xF, false);
+      uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x118, 0xF, 0xF, false);
+      return (lane & 8) ? dn : up;
+    }
+    case 16:
+      return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);
+    default: {
+      auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+      return lane < 32 ? p[1] : p[0];
+    }
+  }
+}
+
+__device__ __forceinline__ float xor_f(float v, int m, int lane) {
+  return __uint_as_float(xor_u32(__float_as_uint(v), m, lane));
+}
 
 __device__ __forceinline__ uint64_t xor64(uint64_t v, int m, int lane) {
-  return bperm64(v, lane ^ m);
+  uint32_t lo = xor_u32((uint32_t)v, m, lane);
+  uint32_t hi = xor_u32((uint32_t)(v >> 32), m, lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Value held by lane + 1 (lane 63 receives garbage: callers overwrite it).
+__device__ __forceinline__ uint64_t next_lane64(uint64_t v) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, 0x130, 0xF, 0xF, false);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), 0x130, 0xF, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ uint64_t kmin(uint64_t a, uint64_t b) { return a < b ? a : b; }

@@ -50,7 +50,7 @@ class Workload:
     k: int
     ef: int
     leaf: int                # leaf bound: a tree node [a,b] with b-a < leaf has no graph
-    degree: int = 16
+    degree: int = 16          # max out-degree R; 32 = the layer-0 bound of HNSW with M = 16
     ef_construction: int = 200
 
 
@@ -60,13 +60,13 @@ WORKLOADS = {
                 "loguniform_frac", 0.01, 0, k=10, ef=64, leaf=128),
     # SIFT-shaped: integer values 0..255 from a clipped, rounded mixture.
     1: Workload(1, "sift-shaped-1M-d128-u8", 1_000_000, 128, 64, "uint8", 10_000,
-                "buckets", 0.0, 11, k=10, ef=64, leaf=1024),
+                "buckets", 0.0, 11, k=10, ef=64, leaf=1024, degree=32),
     # DEEP-shaped batched mix: unit-norm 256-centre mixture, widths 10..N.
     2: Workload(2, "deep-shaped-1M-d96-unit", 1_000_000, 96, 256, "unit", 100_000,
-                "loguniform_pts", 10.0, 0, k=10, ef=64, leaf=1024),
+                "loguniform_pts", 10.0, 0, k=10, ef=64, leaf=1024, degree=32),
     # Embedding-shaped: unit-norm 512-centre mixture in d=768.
     3: Workload(3, "embedding-shaped-2M-d768-unit", 2_000_000, 768, 512, "unit", 20_000,
-                "buckets", 0.0, 13, k=100, ef=256, leaf=1024),
+                "buckets", 0.0, 13, k=100, ef=256, leaf=1024, degree=32),
 }
 
 

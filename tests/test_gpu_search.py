@@ -42,6 +42,19 @@ def tiny(tmp_path_factory):
     gix.free()
 
 
+@pytest.fixture(scope="module")
+def tiny32(tmp_path_factory):
+    """Tiny workload with degree 32 (rows of 32: full-width batches)."""
+    w = synth.make_workload(0, n=6000, nq=120)
+    path = str(tmp_path_factory.mktemp("tiny32") / "tiny32.esgi")
+    esg.build_index(w["X"], w["attr"].astype(np.float64), path, degree=32, leaf=100,
+                    ef_construction=100)
+    gix = esg.Index(path, 0)
+    oix = oracle.read_index(path)
+    yield w, gix, oix, path
+    gix.free()
+
+
 def gpu_search(gix, Q, l, r, k, ef, visited_cap=0, **kw):
     nq = len(Q)
     tr = esg.trace_tensor(nq, DEV)
@@ -195,6 +208,22 @@ def test_tiny_bf16_fp8_traversal(tiny):
         for rer in (0, 1):
             out = gpu_search(gix, Q, l, r, 10, 64, visited_cap=4096, traversal=trav, rerank=rer)
             check_against_oracle(w, oi, out, Q, l, r, 10, 64, kind=kind, rerank=rer)
+
+
+@pytest.mark.parametrize("k,ef,trav", [(10, 64, "f32"), (10, 200, "f32"), (16, 512, "f32"),
+                                       (10, 64, "bf16"), (10, 128, "fp8")])
+def test_degree32_parity(tiny32, k, ef, trav):
+    """Degree-32 graphs: expansions of up to 32 neighbours."""
+    w, gix, oix, path = tiny32
+    kind = {"f32": oracle.DIST_F32, "bf16": oracle.DIST_BF16, "fp8": oracle.DIST_FP8}[trav]
+    oi = oix
+    if trav != "f32":
+        gix.add_storage(trav)
+        oi = oracle.read_index(path)
+        oi = oi.with_bf16() if trav == "bf16" else oi.with_fp8()
+    Q, l, r = w["Q"], w["l"], w["r"]
+    out = gpu_search(gix, Q, l, r, k, ef, visited_cap=8192, traversal=trav, rerank=trav != "f32")
+    check_against_oracle(w, oi, out, Q, l, r, k, ef, kind=kind, rerank=int(trav != "f32"))
 
 
 def test_deterministic_repeat(tiny):
