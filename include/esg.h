@@ -160,15 +160,18 @@ typedef struct {
   int64_t x, y;       /* part of the query range inside the node */
   int64_t hops;       /* expansions of Alg. 1 */
   int64_t n_visited;  /* points whose distance was computed */
+  int64_t ticks;      /* device wall-clock ticks (100 MHz) spent on the part */
 } esg_part_trace;
 
 typedef struct {
   int32_t traversal;     /* ESG_TRAV_*                                     */
   int32_t rerank;        /* recompute final candidates in float32           */
   int32_t cand_cap;      /* capacity of P (0 = ef)                          */
-  int32_t hash_cap;      /* LDS visited-hash entries per wave, a power of two
-                            in [64, 16384] (0 = 2048); beyond 3/4 of it the
-                            search continues exactly with a global bitmap  */
+  int32_t hash_cap;      /* 16-bit LDS visited slots per wave, a power of two
+                            in [64, 16384] (0 = 4096) with
+                            ceil(log2 N) - log2(hash_cap) <= 12 (else
+                            ERANGE); keys that find no free slot within 8
+                            probes go to a global bitmap: always exact    */
   int64_t hop_budget;    /* max expansions per graph part, < 0 = unbounded  */
   esg_part_trace* trace; /* device [nq][2] or NULL                          */
   uint32_t* visited;     /* device [nq][2][visited_cap] or NULL: visited positions */

@@ -54,7 +54,8 @@ class IndexInfo(ctypes.Structure):
 class PartTrace(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("depth", ctypes.c_int32), ("heap", ctypes.c_int64),
                 ("a", ctypes.c_int64), ("b", ctypes.c_int64), ("x", ctypes.c_int64),
-                ("y", ctypes.c_int64), ("hops", ctypes.c_int64), ("n_visited", ctypes.c_int64)]
+                ("y", ctypes.c_int64), ("hops", ctypes.c_int64), ("n_visited", ctypes.c_int64),
+                ("ticks", ctypes.c_int64)]
 
 
 TRACE_FIELDS = [f[0] for f in PartTrace._fields_]
@@ -235,6 +236,6 @@ def decode_trace(t) -> dict:
     a = t.cpu().numpy()
     kd = a[..., 0].copy().view(np.int32).reshape(a.shape[0], a.shape[1], 2)
     out = {"kind": kd[..., 0].astype(np.int64), "depth": kd[..., 1].astype(np.int64)}
-    for i, name in enumerate(["heap", "a", "b", "x", "y", "hops", "n_visited"]):
+    for i, name in enumerate(["heap", "a", "b", "x", "y", "hops", "n_visited", "ticks"]):
         out[name] = a[..., 1 + i]
     return out

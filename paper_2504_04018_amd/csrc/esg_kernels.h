@@ -43,9 +43,7 @@ struct SearchArgs {
   int64_t spill_words;
   int64_t spill_slots;
   uint32_t* counter;      // work-queue head
-  int32_t hash_cap;       // LDS hash entries per wave (power of two)
-  int32_t hash_shift;     // 32 - log2(hash_cap)
-  int32_t hash_limit;     // insertions allowed before spilling
+  int32_t hash_cap;       // 16-bit LDS visited slots per wave (power of two)
   int32_t pad_;
 };
 

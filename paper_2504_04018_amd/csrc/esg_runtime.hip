@@ -20,7 +20,7 @@ ESG_DIMS(ESG_DECLARE_DIM)
 
 namespace {
 
-constexpr int kDefaultHashCap = 2048;
+constexpr int kDefaultHashCap = 4096;
 
 const std::vector<esgk::KernelTable>& kernel_tables() {
   static const std::vector<esgk::KernelTable> tables = [] {
@@ -420,6 +420,12 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   if (cand_cap < 1 || cand_cap > ESG_EF_MAX) return ESG_EINVAL;
   const int hash_cap = o.hash_cap == 0 ? kDefaultHashCap : o.hash_cap;
   if (hash_cap < 64 || hash_cap > 16384 || (hash_cap & (hash_cap - 1)) != 0) return ESG_EINVAL;
+  // a slot stores the low kb - log2(hash_cap) <= 12 bits of a node-local key
+  int tbits = 0;
+  while ((1 << tbits) < hash_cap) tbits++;
+  int kb = 0;
+  while (kb < 32 && ((int64_t)1 << kb) < idx->n) kb++;
+  if (kb - tbits > 12) return ESG_ERANGE;
   if (o.traversal < ESG_TRAV_F32 || o.traversal > ESG_TRAV_FP8) return ESG_EINVAL;
   if (o.traversal == ESG_TRAV_BF16 && !idx->vec16) return ESG_EUNSUPPORTED;
   if (o.traversal == ESG_TRAV_FP8 && !idx->vec8) return ESG_EUNSUPPORTED;
@@ -465,20 +471,16 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   a.spill_slots = idx->spill_slots;
   a.counter = idx->counter;
   a.hash_cap = hash_cap;
-  int lg = 0;
-  while ((1 << lg) < hash_cap) lg++;
-  a.hash_shift = 32 - lg;
-  a.hash_limit = std::min(hash_cap * 3 / 4, hash_cap - 2 * esgk::kBatch);
 
   if (hipSetDevice(idx->device) != hipSuccess) return ESG_EHIP;
-  const size_t lds = (size_t)esgk::kWavesPerGroup * (esgk::kStageBytes + 4 * (size_t)hash_cap);
+  const size_t lds = (size_t)esgk::kWavesPerGroup * (esgk::kStageBytes + 2 * (size_t)hash_cap);
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * esgk::kWavesPerGroup, lds) !=
-          hipSuccess ||
-      per_cu < 1) {
+      hipSuccess) {
     (void)hipGetLastError();
     return ESG_EHIP;
   }
+  if (per_cu < 1) return ESG_ERANGE;  // the LDS request does not fit one CU
   int64_t grid = std::min<int64_t>((nq + esgk::kWavesPerGroup - 1) / esgk::kWavesPerGroup,
                                    (int64_t)per_cu * idx->cu_count);
   grid = std::min<int64_t>(grid, idx->spill_slots / esgk::kWavesPerGroup);

@@ -160,6 +160,7 @@ __device__ __forceinline__ float batch_dist(const SearchArgs& A, uint32_t nid, i
     }
 #pragma unroll
     for (int rr = 0; rr < RF; rr++) {
+      if ((r0 + rr) * VPG >= n_new) break;     // only occupied rounds are reduced
       float acc = 0.0f;
 #pragma unroll
       for (int c = 0; c < CPL; c++) acc = chunk_acc<KIND>(raw[rr][c], qr[c], sc[rr], acc);
@@ -244,6 +245,26 @@ __device__ __forceinline__ void list_pop(uint64_t (&L)[E], int lane) {
   }
 }
 
+// Inserts one key into the sorted list (dropped when its rank is >= cap).
+template <int E>
+__device__ __forceinline__ void list_insert(uint64_t (&L)[E], uint64_t key, int cap, int lane) {
+  int rank = 0;
+#pragma unroll
+  for (int e = 0; e < E; e++) rank += __popcll(ballot(L[e] < key));
+  if (rank >= cap) return;
+  uint64_t carry = kKeyInf;
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    const uint64_t last = readlane64(L[e], 63);
+    uint64_t prev = prev_lane64(L[e]);
+    prev = lane == 0 ? carry : prev;
+    const int i = e * kWave + lane;
+    L[e] = i < rank ? L[e] : (i == rank ? key : prev);
+    if (i >= cap) L[e] = kKeyInf;
+    carry = last;
+  }
+}
+
 template <int E>
 __device__ __forceinline__ uint64_t list_at(const uint64_t (&L)[E], int i) {
   uint64_t v = kKeyInf;
@@ -260,53 +281,99 @@ __device__ __forceinline__ void list_clear(uint64_t (&L)[E]) {
 }
 
 // ---- visited set ------------------------------------------------------------
+//
+// Exact visited set of one graph part [a,b], in LDS with 16-bit slots.
+// A point v has the node-local key k = v - a (< 2^kb, kb = bits of the node
+// size, at least log2 T).  A bijection f on kb bits (odd multiply, then an
+// xor-shift) maps k to f(k); its top log2(T) bits give the home slot and
+// its low rb = kb - log2(T) <= 12 bits are stored, so (home, stored bits)
+// identify k.  A slot holds 0 (empty) or 0x8000 | j << 12 | low bits, where
+// j < 8 is the distance from the home slot (linear probing).  A key whose
+// 8 probe slots are all taken goes to a per-wave bitmap in global memory
+// over [a,b] (cleared on first use); a lookup that meets 8 taken slots
+// without a match consults the bitmap.  Slots are never freed, so both
+// structures stay exact.
 
 struct Visited {
-  uint32_t* table;
-  uint32_t* bm;    // spill bitmap of this wave slot, indexed by position - a
-  uint32_t a;
-  int inserted;    // keys held by the LDS table
+  uint32_t* table;   // T/2 words of two 16-bit slots
+  uint32_t* bm;      // spill bitmap of this wave slot, indexed by position - a
+  uint32_t a, b;
+  uint32_t kb_mask;  // 2^kb - 1
+  int kb, shift;     // shift = kb - log2(T) (stored low bits)
   bool spill;
 };
 
-// Test-and-set of v (lanes with `active`).  True when v was not visited.
-__device__ __forceinline__ bool visit(const SearchArgs& A, Visited& V, uint32_t v, bool active) {
-  if (!active) return false;
-  const uint32_t mask = (uint32_t)A.hash_cap - 1u;
-  uint32_t h = (v * 0x9E3779B1u) >> A.hash_shift;
-  if (!V.spill) {
-    for (;;) {
-      uint32_t old = atomicCAS(&V.table[h], kNoNode, v);
-      if (old == kNoNode) return true;
-      if (old == v) return false;
-      h = (h + 1u) & mask;
-    }
-  }
-  for (;;) {
-    uint32_t cur = V.table[h];
-    if (cur == v) return false;
-    if (cur == kNoNode) break;
-    h = (h + 1u) & mask;
-  }
-  uint32_t off = v - V.a;
-  uint32_t bit = 1u << (off & 31u);
-  uint32_t old = atomicOr(&V.bm[off >> 5], bit);
-  return (old & bit) == 0u;
+__device__ __forceinline__ uint32_t vkey_mix(uint32_t k, const Visited& V) {
+  uint32_t x = (k * 0x9E3779B1u) & V.kb_mask;
+  return x ^ (x >> ((V.kb + 1) >> 1));
 }
 
-__device__ __forceinline__ void visited_reset(const SearchArgs& A, Visited& V, int lane) {
-  for (int i = lane; i < A.hash_cap; i += kWave) V.table[i] = kNoNode;
-  V.inserted = 0;
-  V.spill = false;
-  wave_lds_sync();
-}
-
-// Switch to the global bitmap for node [a,b] before the LDS table overflows.
-__device__ __forceinline__ void visited_spill(Visited& V, uint32_t b, int lane) {
-  const uint32_t words = ((b - V.a) >> 5) + 1u;
+// Clears the bitmap over [a,b] the first time a key spills in this part.
+__device__ __forceinline__ void visited_spill_begin(Visited& V, int lane) {
+  const uint32_t words = ((V.b - V.a) >> 5) + 1u;
   for (uint32_t i = (uint32_t)lane; i < words; i += kWave) V.bm[i] = 0u;
   __threadfence();
   V.spill = true;
+}
+
+// Test-and-set of v for active lanes; true when v was not visited before.
+__device__ __forceinline__ bool visit(const SearchArgs& A, Visited& V, uint32_t v, bool active,
+                                      int lane) {
+  bool is_new = false, overflow = false;
+  if (active) {
+    const uint32_t x = vkey_mix(v - V.a, V);
+    const uint32_t home = x >> V.shift;
+    const uint32_t low = x & ((1u << V.shift) - 1u);
+    const uint32_t tmask = (uint32_t)A.hash_cap - 1u;
+    uint16_t* slots = reinterpret_cast<uint16_t*>(V.table);
+    overflow = true;
+    for (uint32_t j = 0; j < 8u; j++) {
+      const uint32_t s = (home + j) & tmask;
+      const uint32_t want = 0x8000u | (j << 12) | low;
+      uint32_t e = slots[s];
+      if (e == 0u) {
+        // claim the empty slot with a CAS on its 32-bit word
+        uint32_t* word = V.table + (s >> 1);
+        const uint32_t sh = (s & 1u) * 16u;
+        uint32_t old = *word;
+        for (;;) {
+          const uint32_t cur = (old >> sh) & 0xFFFFu;
+          if (cur != 0u) { e = cur; break; }
+          const uint32_t got = atomicCAS(word, old, old | (want << sh));
+          if (got == old) { e = 0u; break; }
+          old = got;
+        }
+        if (e == 0u) { is_new = true; overflow = false; break; }
+      }
+      if (e == want) { overflow = false; break; }   // already visited
+    }
+  }
+  const uint64_t om = ballot(overflow);
+  if (om != 0) {
+    if (!V.spill) visited_spill_begin(V, lane);
+    if (overflow) {
+      const uint32_t off = v - V.a;
+      const uint32_t bit = 1u << (off & 31u);
+      is_new = (atomicOr(&V.bm[off >> 5], bit) & bit) == 0u;
+    }
+  }
+  return is_new;
+}
+
+__device__ __forceinline__ void visited_reset(const SearchArgs& A, Visited& V, uint32_t a,
+                                              uint32_t b, int lane) {
+  V.a = a;
+  V.b = b;
+  int kb = 32 - __clz(b - a);                 // bits of the largest local key
+  const int tbits = 31 - __clz((uint32_t)A.hash_cap);
+  if (kb < tbits) kb = tbits;
+  V.kb = kb;
+  V.kb_mask = kb >= 32 ? 0xFFFFFFFFu : ((1u << kb) - 1u);
+  V.shift = kb - tbits;
+  V.spill = false;
+  uint4* t4 = reinterpret_cast<uint4*>(V.table);
+  for (int i = lane; i < A.hash_cap / 8; i += kWave) t4[i] = make_uint4(0, 0, 0, 0);
+  wave_lds_sync();
 }
 
 // ---- parts ----------------------------------------------------------------------

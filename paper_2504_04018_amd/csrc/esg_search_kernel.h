@@ -5,6 +5,8 @@
 
 namespace esgk {
 
+constexpr int kInsertMax = 4;   // batches with at most this many survivors are inserted one by one
+
 struct PartStats {
   int64_t hops;
   int64_t n_visited;
@@ -20,14 +22,12 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
   uint64_t P[E];
   list_clear(P);
   list_clear(Q);
-  V.a = pt.a;
-  visited_reset(A, V, lane);
+  visited_reset(A, V, pt.a, pt.b, lane);
   const uint32_t* rows = A.adj + (size_t)pt.depth * (size_t)A.n * (size_t)A.R;
   const uint32_t ep = A.ep[pt.heap];
 
   // P <- ep ; Q <- ep when ep is in range (POST)
-  visit(A, V, ep, lane == 0);
-  V.inserted = 1;
+  visit(A, V, ep, lane == 0, lane);
   float dep = batch_dist<KIND, G, CPL>(A, ep, 1, qr, Ls, lane);
   const uint64_t kep = make_key(__uint_as_float(readlane(__float_as_uint(dep), 0)), ep);
   if (lane == 0) {
@@ -51,11 +51,9 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
     hops++;
 
     const uint32_t v = vrow;
-    if (!V.spill && V.inserted + kBatch > A.hash_limit) visited_spill(V, pt.b, lane);
-    const bool is_new = visit(A, V, v, v != kNoNode && v >= pt.a && v <= pt.b);
+    const bool is_new = visit(A, V, v, v != kNoNode && v >= pt.a && v <= pt.b, lane);
     const uint64_t nm = ballot(is_new);
     const int n_new = __popcll(nm);
-    if (!V.spill) V.inserted += n_new;
     if (n_new == 0) {
       u = readlane64(P[0], 0);
       vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
@@ -69,14 +67,35 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
 
     const float bd = batch_dist<KIND, G, CPL>(A, nid, n_new, qr, Ls, lane);
     uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
-    key = sort32(key, lane);
-    // A batch whose best key loses to a full Q can change neither list.
-    const uint64_t kmin0 = readlane64(key, 0);
-    const bool pruned = worst != kKeyInf && worst < kmin0;
+    // A key that loses to a full Q can neither enter Q nor ever be expanded
+    // (the bound only tightens), so dropping it leaves P's useful part, Q
+    // and every later step unchanged.
+    if (worst != kKeyInf && worst < key) key = kKeyInf;
+    const uint64_t sm = ballot(key != kKeyInf);
     const uint64_t p0 = readlane64(P[0], 0);
-    u = pruned ? p0 : kmin(p0, kmin0);                         // min of P after the merge
+    if (sm == 0) {
+      u = p0;
+      vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
+      continue;
+    }
+    if (__popcll(sm) <= kInsertMax) {
+      // few survivors: insert them one by one
+      uint64_t bmin = kKeyInf;
+      for (uint64_t mm = sm; mm; mm &= mm - 1) bmin = kmin(bmin, readlane64(key, __builtin_ctzll(mm)));
+      u = kmin(p0, bmin);
+      vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
+      for (uint64_t mm = sm; mm; mm &= mm - 1) {
+        const uint64_t kj = readlane64(key, __builtin_ctzll(mm));
+        list_insert(P, kj, cap_p, lane);
+        const uint32_t pj = key_pos(kj);
+        if (pj >= pt.x && pj <= pt.y) list_insert(Q, kj, m, lane);
+      }
+      continue;
+    }
+    key = sort32(key, lane);
+    const uint64_t kmin0 = readlane64(key, 0);
+    u = kmin(p0, kmin0);                                       // min of P after the merge
     vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
-    if (pruned) continue;
     list_merge32(P, bperm64(key, 63 - lane), cap_p, lane);
     const uint32_t kp = key_pos(key);
     const bool inr = lane < kBatch && key != kKeyInf && kp >= pt.x && kp <= pt.y;
@@ -103,8 +122,16 @@ __device__ __forceinline__ void scan_leaf(const SearchArgs& A, WaveLds* Ls, cons
     const uint32_t nid = lane < n_new ? base + (uint32_t)lane : kNoNode;
     const float bd = batch_dist<kF32, G32, CPL32>(A, nid, n_new, qr32, Ls, lane);
     uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
-    key = sort32(key, lane);
-    list_merge32(R, bperm64(key, 63 - lane), k, lane);
+    const uint64_t worst = list_at(R, k - 1);
+    if (worst != kKeyInf && worst < key) key = kKeyInf;
+    const uint64_t sm = ballot(key != kKeyInf);
+    if (sm != 0 && __popcll(sm) <= kInsertMax) {
+      for (uint64_t mm = sm; mm; mm &= mm - 1)
+        list_insert(R, readlane64(key, __builtin_ctzll(mm)), k, lane);
+    } else if (sm != 0) {
+      key = sort32(key, lane);
+      list_merge32(R, bperm64(key, 63 - lane), k, lane);
+    }
     if (base > 0xFFFFFFFFu - kBatch) break;
   }
 }
@@ -172,6 +199,7 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
     const Part pt = parts[p];
     uint64_t Qp[E];
     PartStats st{0, 0};
+    const uint64_t t_start = A.trace ? __builtin_amdgcn_s_memrealtime() : 0;
     if (pt.kind == 2) {
       if constexpr (KIND == kF32) scan_leaf<G, CPL, E>(A, Ls, pt, k, qr, Qp, lane);
       else scan_leaf<G32, CPL32, E>(A, Ls, pt, k, qr32, Qp, lane);
@@ -197,6 +225,7 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
       tr.y = pt.y;
       tr.hops = st.hops;
       tr.n_visited = st.n_visited;
+      tr.ticks = (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start);
     }
   }
   if (A.trace && lane == 0 && np < 2) A.trace[qi * 2 + 1].kind = 0;
@@ -216,13 +245,14 @@ __global__ __launch_bounds__(256) void search_kernel(SearchArgs A) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int lane = lane_id();
   const int wid = (int)(threadIdx.x >> 6);
-  WaveLds* Ls = reinterpret_cast<WaveLds*>(smem + (size_t)wid * (kStageBytes + 4 * A.hash_cap));
+  WaveLds* Ls = reinterpret_cast<WaveLds*>(smem + (size_t)wid * (kStageBytes + 2 * A.hash_cap));
   const int64_t slot = (int64_t)blockIdx.x * kWavesPerGroup + wid;
   Visited V;
   V.table = wave_table(Ls);
   V.bm = A.spill + slot * A.spill_words;
-  V.a = 0;
-  V.inserted = 0;
+  V.a = V.b = 0;
+  V.kb = V.shift = 0;
+  V.kb_mask = 0;
   V.spill = false;
   for (;;) {
     uint32_t t = 0;

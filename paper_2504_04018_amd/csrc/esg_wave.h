@@ -104,6 +104,13 @@ __device__ __forceinline__ uint64_t next_lane64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Value held by lane - 1 (lane 0 receives garbage: callers overwrite it).
+__device__ __forceinline__ uint64_t prev_lane64(uint64_t v) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, 0x138, 0xF, 0xF, false);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), 0x138, 0xF, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t kmin(uint64_t a, uint64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ uint64_t kmax(uint64_t a, uint64_t b) { return a < b ? b : a; }
 

@@ -141,7 +141,8 @@ def test_tiny_parity_k_ef(tiny, k, ef):
 
 
 @pytest.mark.parametrize("cap_p,hop_budget,hash_cap", [(1, -1, 0), (128, -1, 0), (64, 0, 0),
-                                                       (64, 7, 0), (64, -1, 64), (32, 50, 128)])
+                                                       (64, 7, 0), (64, -1, 64), (32, 50, 128),
+                                                       (64, -1, 256), (200, -1, 16384)])
 def test_tiny_parity_options(tiny, cap_p, hop_budget, hash_cap):
     """Candidate capacity, hop budget, and a tiny LDS hash that forces the
     exact global-bitmap spill path."""
@@ -242,4 +243,7 @@ def test_argument_errors(tiny):
         assert e.value.status == esg.ESG_EINVAL
     with pytest.raises(esg.EsgError) as e:
         gix.search_ex(Q, l, r, 10, 64, hash_cap=100)
+    assert e.value.status == esg.ESG_EINVAL
+    with pytest.raises(esg.EsgError) as e:
+        gix.search_ex(Q, l, r, 10, 64, hash_cap=32768)
     assert e.value.status == esg.ESG_EINVAL
