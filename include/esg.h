@@ -173,11 +173,51 @@ typedef struct {
                             ERANGE); keys that find no free slot within 8
                             probes go to a global bitmap: always exact    */
   int64_t hop_budget;    /* max expansions per graph part, < 0 = unbounded  */
+  int64_t router_threshold; /* > 0: queries narrower than this many positions
+                            take the MFMA brute-force scan (exact, see
+                            esg_scan_batch); needs bfloat16 storage and a
+                            reservation (esg_index_reserve) of >= nq queries
+                            and windows                                   */
+  int32_t use_graph;     /* 1: capture the launch sequence in a hipGraph on
+                            first use and replay it while the arguments stay
+                            the same                                       */
+  int32_t scan_rerank;   /* candidates recomputed in float32 by the scan
+                            (0 = default)                                  */
   esg_part_trace* trace; /* device [nq][2] or NULL                          */
   uint32_t* visited;     /* device [nq][2][visited_cap] or NULL: visited positions */
   int64_t visited_cap;   /* capacity per part of `visited`                  */
   int64_t* n_invalid;    /* device int64[1] or NULL: += invalid queries     */
 } esg_search_opts;
+
+/* Reserves the device workspace of the brute-force scan and the router:
+ * per-query lists for up to max_queries queries per call and buffers for
+ * up to max_windows windows of at most 2,048 positions (about 10 KB per
+ * window).  Calls with more queries or windows return ERANGE (the router)
+ * or are split into several passes (esg_scan_batch).  Allocates; call it
+ * once before searching.  Errors: EINVAL, ENOMEM. */
+int32_t esg_index_reserve(esg_index* idx, int64_t max_queries, int64_t max_windows);
+
+typedef struct {
+  int32_t rerank_count;  /* candidates recomputed in float32 per query
+                            (0 = min(64E - 1, max(4k, 32)))               */
+  int32_t reserved;
+  int32_t* certified;    /* device int32 [nq] out (1 = certified), or NULL */
+  int64_t* n_fallback;   /* host int64 out: queries rescanned exactly, or NULL */
+} esg_scan_opts;
+
+/* Exact range-filtered k-NN by brute force (Def. 2.1 / 2.2 with the float32
+ * canonical distance, ties by position), for any range widths: candidates
+ * from bfloat16 MFMA dot products (v_mfma_f32_16x16x32_bf16, float32
+ * accumulation) over windows of <= 2,048 positions, float32 rerank, and a
+ * certificate from the rounding-error bound; queries that are not
+ * certified are rescanned exactly.  The result equals a float32 scan of
+ * [l,r].  Same buffers as esg_search_batch; k <= 128.  Copies l and r to
+ * the host to plan the windows and synchronizes `stream` before returning.
+ * Needs bfloat16 storage and a reservation.  Errors: EINVAL, EUNSUPPORTED,
+ * ERANGE, EHIP. */
+int32_t esg_scan_batch(esg_index* idx, const esg_scan_opts* opts, const float* queries,
+                       const int64_t* l, const int64_t* r, int64_t nq, int32_t k,
+                       int64_t* ids, float* dists, void* stream);
 
 /* esg_search_batch with options; opts == NULL behaves like esg_search_batch. */
 int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts,

@@ -65,9 +65,16 @@ TRACE_INT64S = ctypes.sizeof(PartTrace) // 8
 class SearchOpts(ctypes.Structure):
     _fields_ = [("traversal", ctypes.c_int32), ("rerank", ctypes.c_int32),
                 ("cand_cap", ctypes.c_int32), ("hash_cap", ctypes.c_int32),
-                ("hop_budget", ctypes.c_int64), ("trace", ctypes.c_void_p),
+                ("hop_budget", ctypes.c_int64), ("router_threshold", ctypes.c_int64),
+                ("use_graph", ctypes.c_int32), ("scan_rerank", ctypes.c_int32),
+                ("trace", ctypes.c_void_p),
                 ("visited", ctypes.c_void_p), ("visited_cap", ctypes.c_int64),
                 ("n_invalid", ctypes.c_void_p)]
+
+
+class ScanOpts(ctypes.Structure):
+    _fields_ = [("rerank_count", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("certified", ctypes.c_void_p), ("n_fallback", ctypes.c_void_p)]
 
 
 _lib = None
@@ -84,6 +91,8 @@ SIGNATURES = {
     "esg_status_str": (_CP, [_I32]),
     "esg_search_batch": (_I32, [_VP, _VP, _VP, _VP, _I64, _I32, _I32, _VP, _VP, _VP]),
     "esg_search_batch_ex": (_I32, [_VP, _VP, _VP, _VP, _VP, _I64, _I32, _I32, _VP, _VP, _VP]),
+    "esg_index_reserve": (_I32, [_VP, _I64, _I64]),
+    "esg_scan_batch": (_I32, [_VP, _VP, _VP, _VP, _VP, _I64, _I32, _VP, _VP, _VP]),
 }
 
 
@@ -179,6 +188,33 @@ class Index:
             return out[:n * d].reshape(n, d), out[n * d:].view(np.float32)
         return out
 
+    def reserve(self, max_queries: int, max_windows: int) -> None:
+        """esg_index_reserve: workspace of the brute-force scan and the router."""
+        _check(lib().esg_index_reserve(self._h, max_queries, max_windows), "esg_index_reserve")
+
+    def scan(self, queries, l, r, k: int, ids=None, dists=None, rerank_count: int = 0,
+             certified=None, stream=None):
+        """esg_scan_batch: exact range-filtered k-NN; returns (ids, dists, n_fallback)."""
+        import torch
+        nq = queries.shape[0]
+        dev = queries.device
+        qp = _dev(queries, torch.float32, (nq, self.d), "queries")
+        lp = _dev(l, torch.int64, (nq,), "l")
+        rp = _dev(r, torch.int64, (nq,), "r")
+        if ids is None:
+            ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
+        if dists is None:
+            dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        nfb = ctypes.c_int64(0)
+        o = ScanOpts(rerank_count, 0, None if certified is None else certified.data_ptr(),
+                     ctypes.addressof(nfb))
+        st = lib().esg_scan_batch(self._h, ctypes.byref(o), qp, lp, rp, nq, k,
+                                  _dev(ids, torch.int64, (nq, k), "ids"),
+                                  _dev(dists, torch.float32, (nq, k), "dists"),
+                                  _stream_ptr(stream))
+        _check(st, "esg_scan_batch")
+        return ids, dists, nfb.value
+
     def search(self, queries, l, r, k: int, ef: int, ids=None, dists=None, stream=None):
         """esg_search_batch on device tensors; returns (ids int64 [nq,k], dists f32 [nq,k])."""
         return self.search_ex(queries, l, r, k, ef, ids=ids, dists=dists, stream=stream,
@@ -186,7 +222,8 @@ class Index:
 
     def search_ex(self, queries, l, r, k: int, ef: int, traversal: str = "f32",
                   rerank: bool = False, cand_cap: int = 0, hash_cap: int = 0,
-                  hop_budget: int = -1, trace=None, visited=None, visited_cap: int = 0,
+                  hop_budget: int = -1, router_threshold: int = 0, use_graph: bool = False,
+                  scan_rerank: int = 0, trace=None, visited=None, visited_cap: int = 0,
                   n_invalid=None, ids=None, dists=None, stream=None, opts="build"):
         import torch
         nq = queries.shape[0]
@@ -205,6 +242,7 @@ class Index:
                                         _stream_ptr(stream))
         else:
             o = SearchOpts(TRAV[traversal], int(rerank), cand_cap, hash_cap, hop_budget,
+                           router_threshold, int(use_graph), scan_rerank,
                            None if trace is None else trace.data_ptr(),
                            None if visited is None else visited.data_ptr(),
                            visited_cap, None if n_invalid is None else n_invalid.data_ptr())

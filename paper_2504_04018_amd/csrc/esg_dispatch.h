@@ -6,9 +6,15 @@ namespace esgk {
 constexpr int kNumKinds = 3;    // float32, bfloat16, fp8 traversal
 constexpr int kNumWidths = 5;   // list words per lane E = 1, 2, 4, 8, 16
 
+constexpr int kNumScanWidths = 3;  // scan candidate lists of 64, 128, 256 keys
+
 struct KernelTable {
   int dim;
   const void* fn[kNumKinds][kNumWidths];
+  const void* mfma;                       // MFMA approximate distances
+  const void* select[kNumScanWidths];     // per-window top list
+  const void* rerank[kNumScanWidths];     // merge + float32 rerank + certificate
+  const void* fallback[kNumScanWidths];   // exact float32 scan
 };
 
 }  // namespace esgk

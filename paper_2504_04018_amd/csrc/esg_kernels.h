@@ -43,6 +43,8 @@ struct SearchArgs {
   int64_t spill_words;
   int64_t spill_slots;
   uint32_t* counter;      // work-queue head
+  const int32_t* qlist;   // queries to process (null = 0..nq-1)
+  const int32_t* qcount;  // device count of qlist (null = nq)
   int32_t hash_cap;       // 16-bit LDS visited slots per wave (power of two)
   int32_t pad_;
 };

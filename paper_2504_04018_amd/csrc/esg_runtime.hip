@@ -13,6 +13,7 @@
 #include "esg_dispatch.h"
 #include "esg_format.h"
 #include "esg_kernels.h"
+#include "esg_scan_impl.h"
 
 #define ESG_DECLARE_DIM(d) extern "C" void esg_register_dim_##d(esgk::KernelTable*);
 ESG_DIMS(ESG_DECLARE_DIM)
@@ -69,6 +70,31 @@ struct esg_index {
   uint32_t* spill = nullptr;
   int64_t spill_words = 0, spill_slots = 0;
   uint32_t* counter = nullptr;
+  // brute-force scan: norms and rounding statistics of the bfloat16 copy
+  float* norm2 = nullptr;
+  float* stats = nullptr;       // [0] max |x|, [1] max relative bfloat16 rounding error
+  float maxnorm = 0.0f, delta_x = 0.0f;
+  // reserved workspace (esg_index_reserve)
+  int64_t res_queries = 0, res_windows = 0;
+  int32_t* win_q = nullptr;
+  int64_t* win_s = nullptr;
+  int64_t* win_e = nullptr;
+  int32_t* win_order = nullptr;
+  int32_t* q_win0 = nullptr;
+  int32_t* q_nwin = nullptr;
+  int32_t* qlist = nullptr;
+  int32_t* wide = nullptr;
+  int32_t* counts = nullptr;    // [0] narrow, [1] wide, [2] fallback, [3..] bucket histogram
+  int32_t* fb_list = nullptr;
+  float* dist_buf = nullptr;
+  uint64_t* cand = nullptr;
+  int nbuckets = 0, bucket_shift = 11;
+  hipStream_t capture_stream = nullptr;
+  struct GraphEntry {
+    std::vector<uint8_t> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<GraphEntry> graphs;
   int cu_count = 0;
   int64_t device_bytes = 0;
   const esgk::KernelTable* kt = nullptr;
@@ -85,6 +111,11 @@ struct esg_index {
     return ESG_OK;
   }
   void release() {
+    for (auto& g : graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    capture_stream = nullptr;
     for (void* p : allocations) (void)hipFree(p);
     allocations.clear();
   }
@@ -140,6 +171,92 @@ __global__ void encode_fp8_kernel(const float* __restrict__ x, int64_t n, int32_
       if (v < 0.0f && code != 0u) code |= 0x80u;
     }
     yr[j] = (uint8_t)code;
+  }
+}
+
+// |x|^2 per row (float32), the largest |x| and the largest relative
+// bfloat16 rounding error of any element.  One wave per row.
+__global__ void norms_kernel(const float* __restrict__ x, const uint16_t* __restrict__ xb,
+                             int64_t n, int32_t d, int32_t dp, float* __restrict__ norm2,
+                             float* __restrict__ stats) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  float s = 0.0f, rel = 0.0f;
+  for (int j = lane; j < d; j += 64) {
+    const float v = x[row * dp + j];
+    s = __builtin_fmaf(v, v, s);
+    const float vb = __uint_as_float((uint32_t)xb[row * dp + j] << 16);
+    if (v != 0.0f) rel = fmaxf(rel, fabsf(vb - v) / fabsf(v));
+  }
+  for (int m = 32; m >= 1; m >>= 1) {
+    s += __shfl_xor(s, m);
+    rel = fmaxf(rel, __shfl_xor(rel, m));
+  }
+  if (lane == 0) {
+    norm2[row] = s;
+    atomicMax(reinterpret_cast<unsigned int*>(stats), __float_as_uint(sqrtf(s)));
+    atomicMax(reinterpret_cast<unsigned int*>(stats) + 1, __float_as_uint(rel));
+  }
+}
+
+__global__ void zero_i32_kernel(int32_t* p, int32_t count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0;
+}
+
+// Router: queries narrower than `thr` become one scan window each; the rest
+// (and invalid ranges) go to the graph search list.
+__global__ void classify_kernel(const int64_t* __restrict__ l, const int64_t* __restrict__ r,
+                                int64_t nq, int64_t n, int64_t thr, int32_t* win_q,
+                                int64_t* win_s, int64_t* win_e, int32_t* q_win0,
+                                int32_t* q_nwin, int32_t* wide, int32_t* counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const int64_t a = l[i], b = r[i];
+  const bool valid = a >= 0 && b < n && a <= b;
+  if (valid && b - a + 1 < thr) {
+    const int32_t slot = atomicAdd(&counts[0], 1);
+    win_q[slot] = (int32_t)i;
+    win_s[slot] = a;
+    win_e[slot] = b;
+    q_win0[i] = slot;
+    q_nwin[i] = 1;
+  } else {
+    const int32_t slot = atomicAdd(&counts[1], 1);
+    wide[slot] = (int32_t)i;
+  }
+}
+
+__global__ void bucket_hist_kernel(const int64_t* __restrict__ win_s, const int32_t* counts,
+                                   int32_t shift, int32_t* hist) {
+  const int64_t nw = counts[0];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
+       i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&hist[win_s[i] >> shift], 1);
+}
+
+// Exclusive prefix sum of nb <= 1024 bucket counts, in place (one block).
+__global__ void bucket_scan_kernel(int32_t* hist, int32_t nb) {
+  __shared__ int32_t buf[1024];
+  const int t = threadIdx.x;
+  buf[t] = t < nb ? hist[t] : 0;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t v = t >= off ? buf[t - off] : 0;
+    __syncthreads();
+    buf[t] += v;
+    __syncthreads();
+  }
+  if (t < nb) hist[t] = buf[t] - (t < nb ? hist[t] : 0);
+}
+
+__global__ void bucket_scatter_kernel(const int64_t* __restrict__ win_s, const int32_t* counts,
+                                      int32_t shift, int32_t* cursor, int32_t* order) {
+  const int64_t nw = counts[0];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t pos = atomicAdd(&cursor[win_s[i] >> shift], 1);
+    order[pos] = (int32_t)i;
   }
 }
 
@@ -389,8 +506,19 @@ int32_t esg_index_add_storage(esg_index* idx, int32_t kind, void* stream) {
   if (kind == ESG_TRAV_BF16) {
     if (idx->vec16) return ESG_OK;
     int32_t st = idx->alloc((void**)&idx->vec16, (size_t)count * 2);
+    if (st == ESG_OK) st = idx->alloc((void**)&idx->norm2, (size_t)idx->n * 4);
+    if (st == ESG_OK) st = idx->alloc((void**)&idx->stats, 256);
     if (st != ESG_OK) return st;
     encode_bf16_kernel<<<4096, 256, 0, s>>>(idx->vec, idx->vec16, count);
+    zero_i32_kernel<<<1, 64, 0, s>>>(reinterpret_cast<int32_t*>(idx->stats), 64);
+    norms_kernel<<<(unsigned)((idx->n + 3) / 4), 256, 0, s>>>(idx->vec, idx->vec16, idx->n, idx->d,
+                                                            idx->dp, idx->norm2, idx->stats);
+    float host_stats[2] = {0.0f, 0.0f};
+    if (hipMemcpyAsync(host_stats, idx->stats, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return ESG_EHIP;
+    idx->maxnorm = host_stats[0];
+    idx->delta_x = host_stats[1];
   } else {
     if (idx->vec8) return ESG_OK;
     int32_t st = idx->alloc((void**)&idx->vec8, (size_t)count);
@@ -403,6 +531,251 @@ int32_t esg_index_add_storage(esg_index* idx, int32_t kind, void* stream) {
   if (hipGetLastError() != hipSuccess) return ESG_EHIP;
   return ESG_OK;
 }
+
+int32_t esg_index_reserve(esg_index* idx, int64_t max_queries, int64_t max_windows) {
+  if (!idx || max_queries < 1 || max_windows < 1 || max_queries > 0x7FFFFFFF ||
+      max_windows > 0x7FFFFFFF)
+    return ESG_EINVAL;
+  if (max_queries <= idx->res_queries && max_windows <= idx->res_windows) return ESG_OK;
+  if (idx->res_queries > 0) return ESG_EINVAL;  // one reservation per index
+  if (hipSetDevice(idx->device) != hipSuccess) return ESG_EHIP;
+  int shift = 11;
+  while (((idx->n - 1) >> shift) + 1 > 1024) shift++;
+  idx->bucket_shift = shift;
+  idx->nbuckets = (int)(((idx->n - 1) >> shift) + 1);
+  const size_t Q = (size_t)max_queries, W = (size_t)std::max(max_windows, max_queries);
+  int32_t st = ESG_OK;
+  auto A = [&](void** p, size_t b) {
+    if (st == ESG_OK) st = idx->alloc(p, b);
+  };
+  A((void**)&idx->win_q, W * 4);
+  A((void**)&idx->win_s, W * 8);
+  A((void**)&idx->win_e, W * 8);
+  A((void**)&idx->win_order, W * 4);
+  A((void**)&idx->q_win0, Q * 4);
+  A((void**)&idx->q_nwin, Q * 4);
+  A((void**)&idx->qlist, Q * 4);
+  A((void**)&idx->wide, Q * 4);
+  A((void**)&idx->fb_list, Q * 4);
+  A((void**)&idx->counts, (size_t)(4 + idx->nbuckets) * 4);
+  A((void**)&idx->dist_buf, W * esgk::kWin * 4);
+  A((void**)&idx->cand, W * 256 * 8);
+  if (st != ESG_OK) return st;
+  if (hipStreamCreateWithFlags(&idx->capture_stream, hipStreamNonBlocking) != hipSuccess)
+    return ESG_EHIP;
+  idx->res_queries = (int64_t)Q;
+  idx->res_windows = (int64_t)W;
+  return ESG_OK;
+}
+
+namespace {
+
+int scan_width_index(int k) { return k <= 32 ? 0 : (k <= 64 ? 1 : 2); }
+
+esgk::ScanArgs scan_args(esg_index* idx, const float* queries, const int64_t* l, const int64_t* r,
+                         int64_t nq, int32_t k, int32_t mr, int64_t* ids, float* dists,
+                         int32_t* certified) {
+  esgk::ScanArgs S;
+  std::memset(&S, 0, sizeof(S));
+  S.vec = idx->vec;
+  S.vec16 = idx->vec16;
+  S.norm2 = idx->norm2;
+  S.ext_id = idx->ext_id;
+  S.n = idx->n;
+  S.d = idx->d;
+  S.dp = idx->dp;
+  S.queries = queries;
+  S.l = l;
+  S.r = r;
+  S.nq = nq;
+  S.k = k;
+  S.mr = mr;
+  S.win_q = idx->win_q;
+  S.win_s = idx->win_s;
+  S.win_e = idx->win_e;
+  S.win_order = idx->win_order;
+  S.q_win0 = idx->q_win0;
+  S.q_nwin = idx->q_nwin;
+  S.dist_buf = idx->dist_buf;
+  S.cand = idx->cand;
+  S.cand_stride = 256;
+  S.ids = ids;
+  S.dists = dists;
+  S.fb_list = idx->fb_list;
+  S.fb_count = idx->counts + 2;
+  S.certified = certified;
+  S.delta_x = idx->delta_x;
+  S.maxnorm = idx->maxnorm;
+  S.gamma = (float)(idx->d + 4) * 5.9604645e-8f;
+  S.g_rel = 1.0f / 65536.0f;
+  return S;
+}
+
+int32_t launch_fn(const void* fn, int64_t grid, size_t lds, void* arg, hipStream_t s) {
+  if (grid <= 0) return ESG_OK;
+  void* args[] = {arg};
+  if (hipLaunchKernel(fn, dim3((unsigned)grid), dim3(256), args, lds, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return ESG_EHIP;
+  }
+  return ESG_OK;
+}
+
+// The four scan kernels over windows already described in the workspace.
+int32_t launch_scan(esg_index* idx, esgk::ScanArgs& S, int64_t nw_bound, int64_t nq_bound,
+                    hipStream_t s) {
+  const int wi = scan_width_index(S.k);
+  int32_t st = launch_fn(idx->kt->mfma, (nw_bound + 63) / 64, 0, &S, s);
+  if (st == ESG_OK) st = launch_fn(idx->kt->select[wi], (nw_bound + 3) / 4, 0, &S, s);
+  if (st == ESG_OK)
+    st = launch_fn(idx->kt->rerank[wi], (nq_bound + 3) / 4, 4 * esgk::kStageBytes, &S, s);
+  if (st == ESG_OK)
+    st = launch_fn(idx->kt->fallback[wi], std::min<int64_t>(1024, (nq_bound + 3) / 4),
+                   4 * esgk::kStageBytes, &S, s);
+  return st;
+}
+
+}  // namespace
+
+int32_t esg_scan_batch(esg_index* idx, const esg_scan_opts* opts, const float* queries,
+                       const int64_t* l, const int64_t* r, int64_t nq, int32_t k, int64_t* ids,
+                       float* dists, void* stream) {
+  if (!idx || nq < 0) return ESG_EINVAL;
+  if (nq == 0) return ESG_OK;
+  if (!queries || !l || !r || !ids || !dists || k < 1 || k > 128) return ESG_EINVAL;
+  if (!idx->vec16 || !idx->norm2 || !idx->kt->mfma) return ESG_EUNSUPPORTED;
+  if (idx->res_queries < 1) return ESG_ERANGE;
+  if (nq > idx->res_queries) return ESG_ERANGE;
+  esg_scan_opts o;
+  std::memset(&o, 0, sizeof(o));
+  if (opts) o = *opts;
+  const int cap = 64 << scan_width_index(k);
+  const int mr = o.rerank_count > 0 ? o.rerank_count : std::min(cap - 1, std::max(4 * k, 32));
+  if (mr < k || mr > cap - 1) return ESG_EINVAL;
+  if (hipSetDevice(idx->device) != hipSuccess) return ESG_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<int64_t> hl((size_t)nq), hr((size_t)nq);
+  if (hipMemcpyAsync(hl.data(), l, (size_t)nq * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(hr.data(), r, (size_t)nq * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return ESG_EHIP;
+  std::vector<int32_t> q0((size_t)nq, 0), qn((size_t)nq, 0);
+  int64_t n_fallback = 0;
+  int64_t qa = 0;
+  while (qa < nq) {
+    // one pass: queries [qa, qb) whose windows fit the reservation
+    std::vector<int32_t> wq, order, qlist;
+    std::vector<int64_t> wsv, wev;
+    int64_t qb = qa;
+    for (; qb < nq; qb++) {
+      const int64_t a = hl[(size_t)qb], b = hr[(size_t)qb];
+      const bool valid = a >= 0 && b < idx->n && a <= b;
+      const int64_t nwq = valid ? (b - a + esgk::kWin) / esgk::kWin : 0;
+      if ((int64_t)wq.size() + nwq > idx->res_windows && qb > qa) break;
+      if (nwq > idx->res_windows) return ESG_ERANGE;
+      q0[(size_t)qb] = (int32_t)wq.size();
+      qn[(size_t)qb] = (int32_t)nwq;
+      for (int64_t j = 0; j < nwq; j++) {
+        wq.push_back((int32_t)qb);
+        wsv.push_back(a + j * esgk::kWin);
+        wev.push_back(std::min(b, a + (j + 1) * esgk::kWin - 1));
+      }
+      qlist.push_back((int32_t)qb);
+    }
+    const int64_t nw = (int64_t)wq.size();
+    order.resize((size_t)nw);
+    for (int64_t i = 0; i < nw; i++) order[(size_t)i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t u, int32_t v) { return wsv[(size_t)u] < wsv[(size_t)v]; });
+    bool ok = true;
+    if (nw > 0)
+      ok = hipMemcpyAsync(idx->win_q, wq.data(), nw * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
+           hipMemcpyAsync(idx->win_s, wsv.data(), nw * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+           hipMemcpyAsync(idx->win_e, wev.data(), nw * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
+           hipMemcpyAsync(idx->win_order, order.data(), nw * 4, hipMemcpyHostToDevice, s) ==
+               hipSuccess;
+    ok = ok &&
+         hipMemcpyAsync(idx->q_win0, q0.data(), (size_t)nq * 4, hipMemcpyHostToDevice, s) ==
+             hipSuccess &&
+         hipMemcpyAsync(idx->q_nwin, qn.data(), (size_t)nq * 4, hipMemcpyHostToDevice, s) ==
+             hipSuccess &&
+         hipMemcpyAsync(idx->qlist, qlist.data(), qlist.size() * 4, hipMemcpyHostToDevice, s) ==
+             hipSuccess;
+    if (!ok) return ESG_EHIP;
+    zero_i32_kernel<<<1, 64, 0, s>>>(idx->counts, 4);
+    esgk::ScanArgs S = scan_args(idx, queries, l, r, nq, k, mr, ids, dists, o.certified);
+    S.qlist = idx->qlist;
+    S.nw = nw;
+    S.nq_list = (int64_t)qlist.size();
+    int32_t st = launch_scan(idx, S, nw, (int64_t)qlist.size(), s);
+    if (st != ESG_OK) return st;
+    int32_t nfb = 0;
+    if (hipMemcpyAsync(&nfb, idx->counts + 2, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return ESG_EHIP;
+    n_fallback += nfb;
+    qa = qb;
+  }
+  if (o.n_fallback) *o.n_fallback = n_fallback;
+  return ESG_OK;
+}
+
+namespace {
+
+int32_t launch_search(esg_index* idx, const esgk::SearchArgs& a0, const void* fn, size_t lds,
+                      int64_t nq_bound, hipStream_t s) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * esgk::kWavesPerGroup, lds) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return ESG_EHIP;
+  }
+  if (per_cu < 1) return ESG_ERANGE;  // the LDS request does not fit one CU
+  int64_t grid = std::min<int64_t>((nq_bound + esgk::kWavesPerGroup - 1) / esgk::kWavesPerGroup,
+                                   (int64_t)per_cu * idx->cu_count);
+  grid = std::min<int64_t>(grid, idx->spill_slots / esgk::kWavesPerGroup);
+  reset_counter_kernel<<<1, 1, 0, s>>>(idx->counter);
+  esgk::SearchArgs a = a0;
+  void* args[] = {&a};
+  if (hipLaunchKernel(fn, dim3((unsigned)grid), dim3(64 * esgk::kWavesPerGroup), args, lds, s) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return ESG_EHIP;
+  }
+  return ESG_OK;
+}
+
+// Router: narrow queries take the scan, the rest the graph search.  Every
+// size the host needs is an upper bound (nq), so the sequence can be
+// captured in a graph; the kernels read the actual counts on the device.
+int32_t launch_routed(esg_index* idx, const esgk::SearchArgs& a, const void* fn, size_t lds,
+                      int64_t thr, int32_t mr, hipStream_t s) {
+  const int64_t nq = a.nq;
+  zero_i32_kernel<<<1, 1024, 0, s>>>(idx->counts, 4 + idx->nbuckets);
+  classify_kernel<<<(unsigned)((nq + 255) / 256), 256, 0, s>>>(
+      a.l, a.r, nq, idx->n, thr, idx->win_q, idx->win_s, idx->win_e, idx->q_win0, idx->q_nwin,
+      idx->wide, idx->counts);
+  const unsigned sgrid = (unsigned)std::min<int64_t>(1024, (nq + 255) / 256);
+  bucket_hist_kernel<<<sgrid, 256, 0, s>>>(idx->win_s, idx->counts, idx->bucket_shift,
+                                           idx->counts + 4);
+  bucket_scan_kernel<<<1, 1024, 0, s>>>(idx->counts + 4, idx->nbuckets);
+  bucket_scatter_kernel<<<sgrid, 256, 0, s>>>(idx->win_s, idx->counts, idx->bucket_shift,
+                                              idx->counts + 4, idx->win_order);
+  esgk::ScanArgs S = scan_args(idx, a.queries, a.l, a.r, nq, a.k, mr, a.ids, a.dists, nullptr);
+  S.qlist = idx->win_q;          // narrow window i belongs to query win_q[i]
+  S.n_win_dev = idx->counts;
+  S.n_q_dev = idx->counts;
+  S.nw = nq;
+  S.nq_list = nq;
+  int32_t st = launch_scan(idx, S, nq, nq, s);
+  if (st != ESG_OK) return st;
+  esgk::SearchArgs w = a;
+  w.qlist = idx->wide;
+  w.qcount = idx->counts + 1;
+  return launch_search(idx, w, fn, lds, nq, s);
+}
+
+}  // namespace
 
 int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const float* queries,
                             const int64_t* l, const int64_t* r, int64_t nq, int32_t k, int32_t ef,
@@ -431,6 +804,16 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   if (o.traversal == ESG_TRAV_FP8 && !idx->vec8) return ESG_EUNSUPPORTED;
   if ((o.trace || o.visited) && nq > ((int64_t)1 << 40)) return ESG_ERANGE;
   if (o.visited && o.visited_cap < 1) return ESG_EINVAL;
+  int32_t mr = 0;
+  if (o.router_threshold > 0) {
+    if (!idx->vec16 || !idx->norm2) return ESG_EUNSUPPORTED;
+    if (k > 128) return ESG_EINVAL;
+    if (nq > idx->res_queries || nq > idx->res_windows) return ESG_ERANGE;
+    if (o.router_threshold > esgk::kWin) return ESG_EINVAL;
+    const int cap = 64 << scan_width_index(k);
+    mr = o.scan_rerank > 0 ? o.scan_rerank : std::min(cap - 1, std::max(4 * k, 32));
+    if (mr < k || mr > cap - 1) return ESG_EINVAL;
+  }
 
   const void* fn = idx->kt->fn[o.traversal][width_index(std::max(ef, cand_cap))];
   if (!fn) return ESG_EUNSUPPORTED;
@@ -474,21 +857,49 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
 
   if (hipSetDevice(idx->device) != hipSuccess) return ESG_EHIP;
   const size_t lds = (size_t)esgk::kWavesPerGroup * (esgk::kStageBytes + 2 * (size_t)hash_cap);
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * esgk::kWavesPerGroup, lds) !=
-      hipSuccess) {
-    (void)hipGetLastError();
-    return ESG_EHIP;
-  }
-  if (per_cu < 1) return ESG_ERANGE;  // the LDS request does not fit one CU
-  int64_t grid = std::min<int64_t>((nq + esgk::kWavesPerGroup - 1) / esgk::kWavesPerGroup,
-                                   (int64_t)per_cu * idx->cu_count);
-  grid = std::min<int64_t>(grid, idx->spill_slots / esgk::kWavesPerGroup);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  reset_counter_kernel<<<1, 1, 0, s>>>(idx->counter);
-  void* args[] = {&a};
-  if (hipLaunchKernel(fn, dim3((unsigned)grid), dim3(64 * esgk::kWavesPerGroup), args, lds, s) !=
-      hipSuccess) {
+  auto sequence = [&](hipStream_t st) -> int32_t {
+    return o.router_threshold > 0 ? launch_routed(idx, a, fn, lds, o.router_threshold, mr, st)
+                                  : launch_search(idx, a, fn, lds, nq, st);
+  };
+  if (!o.use_graph) return sequence(s);
+
+  // hipGraph: capture once per argument set on the library's own stream,
+  // replay on the caller's stream.
+  if (!idx->capture_stream &&
+      hipStreamCreateWithFlags(&idx->capture_stream, hipStreamNonBlocking) != hipSuccess)
+    return ESG_EHIP;
+  std::vector<uint8_t> key(sizeof(a) + sizeof(o) + 8);
+  std::memcpy(key.data(), &a, sizeof(a));
+  std::memcpy(key.data() + sizeof(a), &o, sizeof(o));
+  std::memcpy(key.data() + sizeof(a) + sizeof(o), &mr, 4);
+  hipGraphExec_t exec = nullptr;
+  for (auto& g : idx->graphs)
+    if (g.key == key) exec = g.exec;
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(idx->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return ESG_EHIP;
+    const int32_t st = sequence(idx->capture_stream);
+    const hipError_t e = hipStreamEndCapture(idx->capture_stream, &graph);
+    if (st != ESG_OK || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      return st != ESG_OK ? st : ESG_EHIP;
+    }
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      (void)hipGetLastError();
+      return ESG_EHIP;
+    }
+    if (idx->graphs.size() >= 16) {
+      (void)hipGraphExecDestroy(idx->graphs.front().exec);
+      idx->graphs.erase(idx->graphs.begin());
+    }
+    idx->graphs.push_back({key, exec});
+  }
+  if (hipGraphLaunch(exec, s) != hipSuccess) {
     (void)hipGetLastError();
     return ESG_EHIP;
   }

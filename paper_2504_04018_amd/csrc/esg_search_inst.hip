@@ -1,6 +1,6 @@
 // Instantiates the search kernels for one vector dimension (-DESG_DIM=d).
 #include "esg_dispatch.h"
-#include "esg_search_kernel.h"
+#include "esg_scan_impl.h"
 
 #ifndef ESG_DIM
 #error "compile with -DESG_DIM=<dimension>"
@@ -38,6 +38,17 @@ void fill(KernelTable* t) {
   t->fn[KIND][4] = kernel_ptr<KIND, 16>();
 }
 
+template <int E>
+void fill_scan(KernelTable* t, int slot) {
+  using S32 = Shape<kF32>;
+  t->select[slot] = reinterpret_cast<const void*>(&select_kernel<E>);
+  t->rerank[slot] = reinterpret_cast<const void*>(&rerank_kernel<S32::G, S32::CPL, E>);
+  t->fallback[slot] = reinterpret_cast<const void*>(&fallback_kernel<S32::G, S32::CPL, E>);
+}
+
+constexpr int kDp = (ESG_DIM + 15) / 16 * 16;
+constexpr int kNK = (kDp + 31) / 32;
+
 }  // namespace
 }  // namespace esgk
 
@@ -49,4 +60,8 @@ extern "C" void ESG_CAT(esg_register_dim_, ESG_DIM)(esgk::KernelTable* t) {
   esgk::fill<esgk::kF32>(t);
   esgk::fill<esgk::kBF16>(t);
   esgk::fill<esgk::kFP8>(t);
+  t->mfma = reinterpret_cast<const void*>(&esgk::mfma_dist_kernel<esgk::kNK>);
+  esgk::fill_scan<1>(t, 0);
+  esgk::fill_scan<2>(t, 1);
+  esgk::fill_scan<4>(t, 2);
 }

@@ -254,11 +254,13 @@ __global__ __launch_bounds__(256) void search_kernel(SearchArgs A) {
   V.kb = V.shift = 0;
   V.kb_mask = 0;
   V.spill = false;
+  const int64_t count = A.qcount ? (int64_t)*A.qcount : A.nq;
   for (;;) {
     uint32_t t = 0;
     if (lane == 0) t = atomicAdd(A.counter, 1u);
-    const int64_t qi = (int64_t)readlane(t, 0);
-    if (qi >= A.nq) break;
+    const int64_t ti = (int64_t)readlane(t, 0);
+    if (ti >= count) break;
+    const int64_t qi = A.qlist ? (int64_t)A.qlist[ti] : ti;
     process_query<KIND, G, CPL, G32, CPL32, E>(A, Ls, V, qi, lane);
   }
 }
