@@ -183,6 +183,20 @@ typedef struct {
                             the same                                       */
   int32_t scan_rerank;   /* candidates recomputed in float32 by the scan
                             (0 = default)                                  */
+  const float* mlp;      /* device ESG_MLP_PARAMS floats, or NULL: the
+                            learned beam width.  Each graph part runs
+                            probe_hops expansions of Alg. 1 with m = ef
+                            (the largest beam), then the network maps 12
+                            features of the search state to y and the part
+                            continues with m = cand_cap = ef' =
+                            clamp(ceil(2^(y + mlp_delta)), k, ef), keeping
+                            the ef' best of P and Q                       */
+  int32_t probe_hops;    /* > 0 with mlp (or with feat_out alone: features
+                            only, no change of beam)                       */
+  float mlp_delta;       /* calibration offset added to y                   */
+  float* feat_out;       /* device float [nq][2][16] or NULL: per graph part
+                            the 12 features, y and ef' (parts that end
+                            before the probe is over are left untouched)  */
   esg_part_trace* trace; /* device [nq][2] or NULL                          */
   uint32_t* visited;     /* device [nq][2][visited_cap] or NULL: visited positions */
   int64_t visited_cap;   /* capacity per part of `visited`                  */
@@ -218,6 +232,31 @@ typedef struct {
 int32_t esg_scan_batch(esg_index* idx, const esg_scan_opts* opts, const float* queries,
                        const int64_t* l, const int64_t* r, int64_t nq, int32_t k,
                        int64_t* ids, float* dists, void* stream);
+
+/* ---- beam-width predictor (learned ef) ------------------------------------
+ * A 12 -> 64 -> 64 -> 1 ReLU network in float32.  Parameters (device
+ * float[ESG_MLP_PARAMS]): W1[64][12] b1[64] W2[64][64] b2[64] W3[64] b3[1]
+ * (ESG_MLP_WEIGHTS trainable values), then the feature mean[12] and
+ * scale[12] used to normalise inputs.  Features (float[n][12]) as written
+ * by feat_out.  Not part of the paper; the training targets come from the
+ * search's own traces (see the Python binding). */
+#define ESG_MLP_FEATURES 12
+#define ESG_MLP_WEIGHTS 5057
+#define ESG_MLP_PARAMS 5081
+#define ESG_MLP_WORKSPACE_FLOATS (512 * 5058)
+
+/* out[i] = network(feats[i]) for i < n.  Device pointers; asynchronous. */
+int32_t esg_mlp_forward(const float* params, const float* feats, int64_t n, float* out,
+                        void* stream);
+/* grad[ESG_MLP_WEIGHTS] = d/dw of mean_i (network(feats[i]) - target[i])^2
+ * and *loss = that mean (device, may be NULL); workspace: device float
+ * [ESG_MLP_WORKSPACE_FLOATS], owned by the caller.  Deterministic. */
+int32_t esg_mlp_grad(const float* params, const float* feats, const float* target, int64_t n,
+                     float* grad, float* loss, float* workspace, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the trainable
+ * weights; m1, m2: device float[ESG_MLP_WEIGHTS] moments, step >= 1. */
+int32_t esg_mlp_adam(float* params, const float* grad, float* m1, float* m2, int64_t step,
+                     float lr, void* stream);
 
 /* esg_search_batch with options; opts == NULL behaves like esg_search_batch. */
 int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts,

@@ -45,7 +45,7 @@ NO_NODE = 0xFFFFFFFF
 def compile_oracle(force: bool = False) -> str:
     """Compile esg_oracle.c into liboracle.so (no fast-math, no contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+        tmp = f"{_LIB}.{os.getpid()}.tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
                                "-fopenmp", "-shared", "-fPIC", "-Wall", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
@@ -94,6 +94,12 @@ def _declare(L):
     L.oracle_search_part.argtypes = [vp, i32, i64, i64, i64, i64, i64, vp, i32, i64, i64, i32,
                                      vp, vp, vp, vp, i64, vp, vp]
     L.oracle_search_part.restype = i32
+    L.oracle_search_part_sw.argtypes = [vp, i32, i64, i64, i64, i64, i64, vp, i32, i64, i64,
+                                        i32, vp, vp, vp, vp, i64, vp, vp, vp]
+    L.oracle_search_part_sw.restype = i32
+    L.oracle_query_sw.argtypes = [vp, vp, i64, i64, i32, i32, i64, i64, i32, i32, i64, vp,
+                                  vp, vp, vp]
+    L.oracle_query_sw.restype = i32
     L.oracle_scan_part.argtypes = [vp, i64, i64, vp, i32, vp, vp, vp]
     L.oracle_scan_part.restype = i32
     L.oracle_query.argtypes = [vp, vp, i64, i64, i32, i32, i64, i64, i32, i32, vp, vp, vp]
@@ -313,6 +319,51 @@ def search_part(ix: OracleIndex, part: dict, q: np.ndarray, m: int, cap_p: int |
     return qd[:L], qp[:L], vis[:min(int(nv[0]), visited_cap)], int(hops[0]), st
 
 
+class _Switch(ctypes.Structure):
+    _fields_ = [("switch_hop", ctypes.c_int64), ("ef2", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("w_query", ctypes.c_int64), ("n_parts", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("feat", ctypes.c_void_p)]
+
+
+def search_part_learned(ix: OracleIndex, part: dict, q, ef_max: int, switch_hop: int, ef2: int,
+                        k: int, w_query: int, n_parts: int, kind: int = DIST_F32,
+                        visited_cap: int = 1 << 22):
+    """Alg. 1 + POST with the learned switch: after switch_hop expansions
+    at m = cap = ef_max, keep the ef2 best of P and Q and continue with
+    m = cap = ef2 (ef2 <= 0: features only).  Returns (dists, positions,
+    visited, hops, status, float64 features (12) or None)."""
+    q = np.ascontiguousarray(q, np.float32)
+    qd = np.zeros(ef_max, np.float32)
+    qp = np.zeros(ef_max, np.int64)
+    ql = np.zeros(1, np.int32)
+    vis = np.zeros(visited_cap, np.int64)
+    nv = np.zeros(1, np.int64)
+    hops = np.zeros(1, np.int64)
+    feat = np.full(12, np.nan)
+    sw = _Switch(switch_hop, ef2, k, w_query, n_parts, 0, feat.ctypes.data)
+    st = lib().oracle_search_part_sw(ix.cstruct(), part["depth"], part["heap"], part["a"],
+                                     part["b"], part["x"], part["y"], _p(q), ef_max, ef_max, -1,
+                                     kind, _p(qd), _p(qp), _p(ql), _p(vis), visited_cap, _p(nv),
+                                     _p(hops), ctypes.byref(sw))
+    L = int(ql[0])
+    return (qd[:L], qp[:L], vis[:min(int(nv[0]), visited_cap)], int(hops[0]), st,
+            None if np.isnan(feat[0]) else feat)
+
+
+def query_learned(ix: OracleIndex, q, lq, rq, k, ef_max, switch_hop, ef2_parts, kind=DIST_F32,
+                  rerank=0):
+    """Alg. 4 where graph part i switches to ef2_parts[i] after switch_hop
+    expansions (the beam widths a predictor chose)."""
+    q = np.ascontiguousarray(q, np.float32)
+    ids = np.zeros(k, np.int64)
+    dists = np.zeros(k, np.float32)
+    stats = np.zeros(8, np.int64)
+    e2 = np.ascontiguousarray(ef2_parts, np.int32)
+    st = lib().oracle_query_sw(ix.cstruct(), _p(q), lq, rq, k, ef_max, ef_max, -1, kind, rerank,
+                               switch_hop, _p(e2), _p(ids), _p(dists), _p(stats))
+    return ids, dists, stats, st
+
+
 def query(ix: OracleIndex, q, lq, rq, k, ef, cap_p=None, hop_budget=-1, kind=DIST_F32, rerank=0):
     q = np.ascontiguousarray(q, np.float32)
     ids = np.zeros(k, np.int64)
@@ -388,3 +439,53 @@ def recall(vec_pos, Q, l, r, pos_found, gt_pos, gt_dist, k):
         rec[i] = min(kk, int(np.sum(df <= dk))) / kk
         strict[i] = len(np.intersect1d(found, gt_pos[i][:kk])) / kk
     return float(rec.mean()), float(strict.mean()), rec
+
+
+# --------------------------------------------------------------------------
+# Beam-width predictor in float64 (forward and manual backward).
+# --------------------------------------------------------------------------
+# Parameter vector layout: W1[64][12] b1[64] W2[64][64] b2[64] W3[64] b3[1]
+# mean[12] scale[12]; loss = mean over samples of (y - t)^2.
+
+MLP_SIZES = [("W1", (64, 12)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (64,)),
+             ("b3", (1,)), ("mu", (12,)), ("sd", (12,))]
+
+
+def mlp_unpack(params):
+    out, o = {}, 0
+    p = np.asarray(params, np.float64)
+    for name, shape in MLP_SIZES:
+        n = int(np.prod(shape))
+        out[name] = p[o:o + n].reshape(shape)
+        o += n
+    return out
+
+
+def mlp_forward64(params, F):
+    P = mlp_unpack(params)
+    X = (np.asarray(F, np.float64) - P["mu"]) / P["sd"]
+    A1 = X @ P["W1"].T + P["b1"]
+    H1 = np.maximum(A1, 0.0)
+    A2 = H1 @ P["W2"].T + P["b2"]
+    H2 = np.maximum(A2, 0.0)
+    return H2 @ P["W3"] + P["b3"][0], (X, A1, H1, A2, H2)
+
+
+def mlp_grad64(params, F, T):
+    """Gradient of mean (y - t)^2 w.r.t. the 5,057 trainable weights, by the
+    chain rule written out layer by layer; returns (grad, loss)."""
+    P = mlp_unpack(params)
+    y, (X, A1, H1, A2, H2) = mlp_forward64(params, F)
+    B = len(y)
+    err = y - np.asarray(T, np.float64)
+    gy = 2.0 * err / B                         # dL/dy
+    gW3 = gy @ H2
+    gb3 = np.array([gy.sum()])
+    gA2 = np.outer(gy, P["W3"]) * (A2 > 0)    # dL/da2
+    gW2 = gA2.T @ H1
+    gb2 = gA2.sum(0)
+    gA1 = (gA2 @ P["W2"]) * (A1 > 0)          # dL/da1
+    gW1 = gA1.T @ X
+    gb1 = gA1.sum(0)
+    grad = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3, gb3])
+    return grad, float(np.mean(err ** 2))

@@ -302,12 +302,68 @@ static cand list_pop_min(sorted_list* l) {
  * [x,y] nearest to q.  Writes the final Q (at most m entries, ascending) to
  * q_dist/q_pos, the visited points (discovery order) to `visited` when it
  * is not NULL, and the number of expansions to *hops. */
+/* Learned beam width (not in the paper): when switch_hop >= 0 and the
+ * search reaches switch_hop expansions, the features of the state are
+ * written to feat (12 doubles, when not NULL) and, when ef2 > 0, P and Q
+ * keep their ef2 best and the search continues with m = cap_p = ef2.
+ * w_query and n_parts describe the whole query; k is the answer size. */
+typedef struct {
+  int64_t switch_hop;
+  int32_t ef2;
+  int32_t k;
+  int64_t w_query;
+  int32_t n_parts;
+  int32_t pad_;
+  double* feat;
+} oracle_switch;
+
+static void probe_features(const oracle_switch* sw, const sorted_list* P, const sorted_list* Q,
+                           int64_t cap_p, int64_t a, int64_t b, int64_t x, int64_t y,
+                           double d_ep, int64_t n_inr, int64_t nv, double* f) {
+  double wp = (double)(y - x + 1), L = (double)(b - a + 1);
+  int64_t kk = sw->k < Q->len ? sw->k : Q->len;
+  double q0 = Q->len > 0 ? (double)Q->a[0].dist : d_ep;
+  double qk = kk > 0 ? (double)Q->a[kk - 1].dist : d_ep;
+  double p0 = (double)P->a[0].dist;
+  double den = d_ep > 0.0 ? d_ep : 1.0;
+  double fill = (double)Q->len / (double)sw->k;
+  f[0] = log2(wp);
+  f[1] = log2(L);
+  f[2] = wp / L;
+  f[3] = log2((double)sw->w_query);
+  f[4] = (double)(sw->n_parts - 1);
+  f[5] = (double)P->len / (double)cap_p;
+  f[6] = fill < 4.0 ? fill : 4.0;
+  f[7] = (double)n_inr / (double)nv;
+  f[8] = q0 / den;
+  f[9] = qk / den;
+  f[10] = qk > 0.0 ? p0 / qk : 1.0;
+  f[11] = log2(1.0 + (double)nv);
+}
+
+int32_t oracle_search_part_sw(const oracle_index* ix, int32_t depth, int64_t heap,
+                              int64_t a, int64_t b, int64_t x, int64_t y, const float* q,
+                              int32_t m, int64_t cap_p, int64_t hop_budget, int32_t kind,
+                              float* q_dist, int64_t* q_pos, int32_t* q_len,
+                              int64_t* visited, int64_t visited_cap, int64_t* n_visited,
+                              int64_t* hops, const oracle_switch* sw);
+
 int32_t oracle_search_part(const oracle_index* ix, int32_t depth, int64_t heap,
                            int64_t a, int64_t b, int64_t x, int64_t y, const float* q,
                            int32_t m, int64_t cap_p, int64_t hop_budget, int32_t kind,
                            float* q_dist, int64_t* q_pos, int32_t* q_len,
                            int64_t* visited, int64_t visited_cap, int64_t* n_visited,
                            int64_t* hops) {
+  return oracle_search_part_sw(ix, depth, heap, a, b, x, y, q, m, cap_p, hop_budget, kind,
+                               q_dist, q_pos, q_len, visited, visited_cap, n_visited, hops, NULL);
+}
+
+int32_t oracle_search_part_sw(const oracle_index* ix, int32_t depth, int64_t heap,
+                              int64_t a, int64_t b, int64_t x, int64_t y, const float* q,
+                              int32_t m, int64_t cap_p, int64_t hop_budget, int32_t kind,
+                              float* q_dist, int64_t* q_pos, int32_t* q_len,
+                              int64_t* visited, int64_t visited_cap, int64_t* n_visited,
+                              int64_t* hops, const oracle_switch* sw) {
   if (m < 1 || cap_p < 1 || depth < 0 || depth >= ix->n_depth) return OR_EINVAL;
   if (!(0 <= a && a <= x && x <= y && y <= b && b < ix->n)) return OR_EINVAL;
   if (heap < 1 || heap >= ((int64_t)1 << ix->n_depth)) return OR_EINVAL;
@@ -322,10 +378,11 @@ int32_t oracle_search_part(const oracle_index* ix, int32_t depth, int64_t heap,
     free(seen);
     return OR_ENOMEM;
   }
-  int64_t nv = 0, h = 0;
+  int64_t nv = 0, h = 0, n_inr = 0;
 
   /* P <- ep ; Q <- ep (POST: only if in range) */
   cand e = {dist_of(ix, kind, ep, q), ep};
+  n_inr = (x <= (int64_t)ep && (int64_t)ep <= y) ? 1 : 0;
   seen[ep - a] = 1;
   if (visited && nv < visited_cap) visited[nv] = ep;
   nv++;
@@ -334,6 +391,16 @@ int32_t oracle_search_part(const oracle_index* ix, int32_t depth, int64_t heap,
 
   int32_t status = OR_OK;
   while (P.len > 0) {
+    if (sw && sw->switch_hop >= 0 && h == sw->switch_hop) {
+      if (sw->feat)
+        probe_features(sw, &P, &Q, cap_p, a, b, x, y, (double)e.dist, n_inr, nv, sw->feat);
+      if (sw->ef2 > 0) {                               /* keep the ef2 best of P and Q */
+        if (P.len > sw->ef2) P.len = sw->ef2;
+        if (Q.len > sw->ef2) Q.len = sw->ef2;
+        m = sw->ef2;
+        cap_p = sw->ef2;
+      }
+    }
     cand u = P.a[0];                                   /* u <- P.top() */
     if (Q.len >= m && cand_less(Q.a[Q.len - 1], u)) break; /* farther than worst of a full Q */
     if (hop_budget >= 0 && h >= hop_budget) break;
@@ -348,6 +415,7 @@ int32_t oracle_search_part(const oracle_index* ix, int32_t depth, int64_t heap,
       if (visited && nv < visited_cap) visited[nv] = v;
       nv++;
       cand c = {dist_of(ix, kind, v, q), v};
+      if (x <= (int64_t)v && (int64_t)v <= y) n_inr++;
       list_insert(&P, c);                               /* P <- P u v */
       if (P.len > cap_p) P.len = cap_p;                 /* drop the largest */
       if ((int64_t)v < x || (int64_t)v > y) continue;   /* POST: out of range */
@@ -399,10 +467,25 @@ int32_t oracle_scan_part(const oracle_index* ix, int64_t x, int64_t y, const flo
  * n_graph_parts, n_scan_parts, status of the worst part, 0, 0.
  * rerank != 0 recomputes the final Q of every graph part in float32 before
  * taking its top k (used with bfloat16 / fp8 traversal). */
+/* Alg. 4 with the learned beam width: graph part i switches to ef2[i]
+ * after switch_hop expansions (ef2[i] <= 0: no switch for that part). */
+int32_t oracle_query_sw(const oracle_index* ix, const float* q, int64_t lq, int64_t rq,
+                        int32_t k, int32_t ef, int64_t cap_p, int64_t hop_budget,
+                        int32_t kind, int32_t rerank, int64_t switch_hop, const int32_t* ef2,
+                        int64_t* ids, float* dists, int64_t* stats);
+
 int32_t oracle_query(const oracle_index* ix, const float* q, int64_t lq, int64_t rq,
                      int32_t k, int32_t ef, int64_t cap_p, int64_t hop_budget,
                      int32_t kind, int32_t rerank, int64_t* ids, float* dists,
                      int64_t* stats) {
+  return oracle_query_sw(ix, q, lq, rq, k, ef, cap_p, hop_budget, kind, rerank, -1, NULL, ids,
+                         dists, stats);
+}
+
+int32_t oracle_query_sw(const oracle_index* ix, const float* q, int64_t lq, int64_t rq,
+                        int32_t k, int32_t ef, int64_t cap_p, int64_t hop_budget,
+                        int32_t kind, int32_t rerank, int64_t switch_hop, const int32_t* ef2,
+                        int64_t* ids, float* dists, int64_t* stats) {
   for (int32_t i = 0; i < k; i++) {
     ids[i] = -1;
     dists[i] = INFINITY;
@@ -428,8 +511,10 @@ int32_t oracle_query(const oracle_index* ix, const float* q, int64_t lq, int64_t
       if (stats) { stats[2] += o[6] - o[5] + 1; stats[4]++; }
     } else {
       int64_t nv = 0, h = 0;
-      st = oracle_search_part(ix, (int32_t)o[1], o[2], o[3], o[4], o[5], o[6], q, ef,
-                              cap_p, hop_budget, kind, pd, pp, &len, NULL, 0, &nv, &h);
+      oracle_switch sw = {switch_hop, ef2 ? ef2[i] : 0, k, rq - lq + 1, np, 0, NULL};
+      st = oracle_search_part_sw(ix, (int32_t)o[1], o[2], o[3], o[4], o[5], o[6], q, ef,
+                                 cap_p, hop_budget, kind, pd, pp, &len, NULL, 0, &nv, &h,
+                                 (switch_hop >= 0 && ef2) ? &sw : NULL);
       if (stats) { stats[1] += h; stats[2] += nv; stats[3]++; }
       if (st == OR_OK && rerank && kind != DIST_F32) {
         sorted_list R;

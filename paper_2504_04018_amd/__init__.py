@@ -67,6 +67,8 @@ class SearchOpts(ctypes.Structure):
                 ("cand_cap", ctypes.c_int32), ("hash_cap", ctypes.c_int32),
                 ("hop_budget", ctypes.c_int64), ("router_threshold", ctypes.c_int64),
                 ("use_graph", ctypes.c_int32), ("scan_rerank", ctypes.c_int32),
+                ("mlp", ctypes.c_void_p), ("probe_hops", ctypes.c_int32),
+                ("mlp_delta", ctypes.c_float), ("feat_out", ctypes.c_void_p),
                 ("trace", ctypes.c_void_p),
                 ("visited", ctypes.c_void_p), ("visited_cap", ctypes.c_int64),
                 ("n_invalid", ctypes.c_void_p)]
@@ -93,7 +95,12 @@ SIGNATURES = {
     "esg_search_batch_ex": (_I32, [_VP, _VP, _VP, _VP, _VP, _I64, _I32, _I32, _VP, _VP, _VP]),
     "esg_index_reserve": (_I32, [_VP, _I64, _I64]),
     "esg_scan_batch": (_I32, [_VP, _VP, _VP, _VP, _VP, _I64, _I32, _VP, _VP, _VP]),
+    "esg_mlp_forward": (_I32, [_VP, _VP, _I64, _VP, _VP]),
+    "esg_mlp_grad": (_I32, [_VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP]),
+    "esg_mlp_adam": (_I32, [_VP, _VP, _VP, _VP, _I64, ctypes.c_float, _VP]),
 }
+MLP_FEATURES, MLP_WEIGHTS, MLP_PARAMS = 12, 5057, 5081
+MLP_WORKSPACE_FLOATS = 512 * 5058
 
 
 def lib() -> ctypes.CDLL:
@@ -223,7 +230,8 @@ class Index:
     def search_ex(self, queries, l, r, k: int, ef: int, traversal: str = "f32",
                   rerank: bool = False, cand_cap: int = 0, hash_cap: int = 0,
                   hop_budget: int = -1, router_threshold: int = 0, use_graph: bool = False,
-                  scan_rerank: int = 0, trace=None, visited=None, visited_cap: int = 0,
+                  scan_rerank: int = 0, mlp=None, probe_hops: int = 0, mlp_delta: float = 0.0,
+                  feat_out=None, trace=None, visited=None, visited_cap: int = 0,
                   n_invalid=None, ids=None, dists=None, stream=None, opts="build"):
         import torch
         nq = queries.shape[0]
@@ -243,6 +251,8 @@ class Index:
         else:
             o = SearchOpts(TRAV[traversal], int(rerank), cand_cap, hash_cap, hop_budget,
                            router_threshold, int(use_graph), scan_rerank,
+                           None if mlp is None else mlp.data_ptr(), probe_hops, mlp_delta,
+                           None if feat_out is None else feat_out.data_ptr(),
                            None if trace is None else trace.data_ptr(),
                            None if visited is None else visited.data_ptr(),
                            visited_cap, None if n_invalid is None else n_invalid.data_ptr())
@@ -277,3 +287,38 @@ def decode_trace(t) -> dict:
     for i, name in enumerate(["heap", "a", "b", "x", "y", "hops", "n_visited", "ticks"]):
         out[name] = a[..., 1 + i]
     return out
+
+
+def mlp_forward(params, feats, out=None, stream=None):
+    """esg_mlp_forward on device tensors (float32 [5081], [n,12]) -> [n]."""
+    import torch
+    n = feats.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=feats.device)
+    _check(lib().esg_mlp_forward(_dev(params, torch.float32, (MLP_PARAMS,), "params"),
+                                 _dev(feats, torch.float32, (n, MLP_FEATURES), "feats"), n,
+                                 _dev(out, torch.float32, (n,), "out"), _stream_ptr(stream)),
+           "esg_mlp_forward")
+    return out
+
+
+def mlp_grad(params, feats, target, grad, loss, workspace, stream=None):
+    """esg_mlp_grad: grad[5057] and loss[1] of the mean squared error."""
+    import torch
+    n = feats.shape[0]
+    _check(lib().esg_mlp_grad(_dev(params, torch.float32, (MLP_PARAMS,), "params"),
+                              _dev(feats, torch.float32, (n, MLP_FEATURES), "feats"),
+                              _dev(target, torch.float32, (n,), "target"), n,
+                              _dev(grad, torch.float32, (MLP_WEIGHTS,), "grad"),
+                              _dev(loss, torch.float32, (1,), "loss"),
+                              _dev(workspace, torch.float32, (MLP_WORKSPACE_FLOATS,), "workspace"),
+                              _stream_ptr(stream)), "esg_mlp_grad")
+
+
+def mlp_adam(params, grad, m1, m2, step, lr, stream=None):
+    import torch
+    _check(lib().esg_mlp_adam(_dev(params, torch.float32, (MLP_PARAMS,), "params"),
+                              _dev(grad, torch.float32, (MLP_WEIGHTS,), "grad"),
+                              _dev(m1, torch.float32, (MLP_WEIGHTS,), "m1"),
+                              _dev(m2, torch.float32, (MLP_WEIGHTS,), "m2"), step, lr,
+                              _stream_ptr(stream)), "esg_mlp_adam")

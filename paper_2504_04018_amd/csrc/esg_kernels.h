@@ -13,6 +13,23 @@ constexpr int kStageBytes = 1024;   // per-wave LDS staging ahead of the hash
 
 enum DistKind : int { kF32 = 0, kBF16 = 1, kFP8 = 2 };
 
+// Beam-width predictor: 12 features -> 64 -> 64 -> 1 (ReLU), float32.
+// Parameter layout: W1[64][12] b1[64] W2[64][64] b2[64] W3[64] b3[1]
+// feature mean[12] feature scale[12].
+constexpr int kFeat = 12;
+constexpr int kHidden = 64;
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kHidden * kFeat;
+constexpr int kOffW2 = kOffB1 + kHidden;
+constexpr int kOffB2 = kOffW2 + kHidden * kHidden;
+constexpr int kOffW3 = kOffB2 + kHidden;
+constexpr int kOffB3 = kOffW3 + kHidden;
+constexpr int kOffMu = kOffB3 + 1;
+constexpr int kOffSd = kOffMu + kFeat;
+constexpr int kMlpParams = kOffSd + kFeat;   // 5081
+constexpr int kMlpWeights = kOffMu;           // 5057 trainable
+constexpr int kFeatStride = 16;               // 12 features, raw output, ef', 2 spare
+
 struct SearchArgs {
   // index (device)
   const float* vec;       // [n][dp] float32, rows zero-padded to dp
@@ -43,6 +60,12 @@ struct SearchArgs {
   int64_t spill_words;
   int64_t spill_slots;
   uint32_t* counter;      // work-queue head
+  // learned beam width: after probe_hops expansions at m = ef the MLP sets
+  // m = cand_cap = ef' for the rest of the part
+  const float* mlp;       // parameters (kMlpParams floats) or null
+  float* feat_out;        // [nq][2][kFeatStride] features, raw output and ef' (optional)
+  int32_t probe_hops;
+  float mlp_delta;        // calibration offset added to the predicted log2(ef)
   const int32_t* qlist;   // queries to process (null = 0..nq-1)
   const int32_t* qcount;  // device count of qlist (null = nq)
   int32_t hash_cap;       // 16-bit LDS visited slots per wave (power of two)

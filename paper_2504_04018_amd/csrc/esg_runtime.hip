@@ -854,6 +854,11 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   a.spill_slots = idx->spill_slots;
   a.counter = idx->counter;
   a.hash_cap = hash_cap;
+  if (o.probe_hops < 0 || (o.mlp && o.probe_hops < 1)) return ESG_EINVAL;
+  a.mlp = o.mlp;
+  a.feat_out = o.feat_out;
+  a.probe_hops = (o.mlp || o.feat_out) ? o.probe_hops : 0;
+  a.mlp_delta = o.mlp_delta;
 
   if (hipSetDevice(idx->device) != hipSuccess) return ESG_EHIP;
   const size_t lds = (size_t)esgk::kWavesPerGroup * (esgk::kStageBytes + 2 * (size_t)hash_cap);

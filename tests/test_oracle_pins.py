@@ -478,3 +478,30 @@ def test_recall_definition():
     bad[0, 0] = -1
     rec2, _, per2 = oracle.recall(X, Q, l, r, bad, gp, gd, 10)
     assert per2[0] == 0.9 and per2[4] == 1.0   # a 1-point range needs only 1 hit
+
+
+# ---------------------------------------------------------------- beam-width network
+
+def test_mlp_backprop_matches_finite_differences():
+    """The float64 manual backward of the 12-64-64-1 ReLU network equals
+    central finite differences of its forward (loss = mean squared error)."""
+    rng = np.random.default_rng(61)
+    params = np.concatenate([rng.standard_normal(5057) * 0.2, rng.standard_normal(12),
+                             np.abs(rng.standard_normal(12)) + 0.5])
+    F = rng.standard_normal((40, 12)) * 2.0
+    T = rng.standard_normal(40)
+    grad, loss = oracle.mlp_grad64(params, F, T)
+
+    def L(p):
+        y, _ = oracle.mlp_forward64(p, F)
+        return np.mean((y - T) ** 2)
+
+    assert abs(L(params) - loss) < 1e-12
+    idx = np.concatenate([rng.choice(768, 30), 768 + rng.choice(64, 8), 832 + rng.choice(4096, 30),
+                          4928 + rng.choice(64, 8), 4992 + rng.choice(64, 10), [5056]])
+    h = 1e-6
+    for j in idx:
+        e = np.zeros_like(params)
+        e[j] = h
+        fd = (L(params + e) - L(params - e)) / (2 * h)
+        assert abs(fd - grad[j]) <= 1e-6 + 1e-5 * abs(fd), (j, fd, grad[j])
