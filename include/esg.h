@@ -194,8 +194,13 @@ typedef struct {
   int32_t probe_hops;    /* > 0 with mlp (or with feat_out alone: features
                             only, no change of beam)                       */
   float mlp_delta;       /* calibration offset added to y                   */
+  int32_t mlp_target;    /* 0: y sets the beam width as above; 1: y sets the
+                            stopping step instead -- the part may take at
+                            most ceil(2^(y + mlp_delta)) (>= 1) further
+                            expansions, m stays ef                        */
   float* feat_out;       /* device float [nq][2][16] or NULL: per graph part
-                            the 12 features, y and ef' (parts that end
+                            the 12 features, y and ef' (or the granted
+                            expansions when mlp_target = 1) (parts that end
                             before the probe is over are left untouched)  */
   esg_part_trace* trace; /* device [nq][2] or NULL                          */
   uint32_t* visited;     /* device [nq][2][visited_cap] or NULL: visited positions */

@@ -97,7 +97,7 @@ def _declare(L):
     L.oracle_search_part_sw.argtypes = [vp, i32, i64, i64, i64, i64, i64, vp, i32, i64, i64,
                                         i32, vp, vp, vp, vp, i64, vp, vp, vp]
     L.oracle_search_part_sw.restype = i32
-    L.oracle_query_sw.argtypes = [vp, vp, i64, i64, i32, i32, i64, i64, i32, i32, i64, vp,
+    L.oracle_query_sw.argtypes = [vp, vp, i64, i64, i32, i32, i64, i64, i32, i32, i64, vp, vp,
                                   vp, vp, vp]
     L.oracle_query_sw.restype = i32
     L.oracle_scan_part.argtypes = [vp, i64, i64, vp, i32, vp, vp, vp]
@@ -322,7 +322,7 @@ def search_part(ix: OracleIndex, part: dict, q: np.ndarray, m: int, cap_p: int |
 class _Switch(ctypes.Structure):
     _fields_ = [("switch_hop", ctypes.c_int64), ("ef2", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("w_query", ctypes.c_int64), ("n_parts", ctypes.c_int32), ("pad_", ctypes.c_int32),
-                ("feat", ctypes.c_void_p)]
+                ("feat", ctypes.c_void_p), ("hop2", ctypes.c_int64)]
 
 
 def search_part_learned(ix: OracleIndex, part: dict, q, ef_max: int, switch_hop: int, ef2: int,
@@ -340,7 +340,7 @@ def search_part_learned(ix: OracleIndex, part: dict, q, ef_max: int, switch_hop:
     nv = np.zeros(1, np.int64)
     hops = np.zeros(1, np.int64)
     feat = np.full(12, np.nan)
-    sw = _Switch(switch_hop, ef2, k, w_query, n_parts, 0, feat.ctypes.data)
+    sw = _Switch(switch_hop, ef2, k, w_query, n_parts, 0, feat.ctypes.data, 0)
     st = lib().oracle_search_part_sw(ix.cstruct(), part["depth"], part["heap"], part["a"],
                                      part["b"], part["x"], part["y"], _p(q), ef_max, ef_max, -1,
                                      kind, _p(qd), _p(qp), _p(ql), _p(vis), visited_cap, _p(nv),
@@ -351,16 +351,18 @@ def search_part_learned(ix: OracleIndex, part: dict, q, ef_max: int, switch_hop:
 
 
 def query_learned(ix: OracleIndex, q, lq, rq, k, ef_max, switch_hop, ef2_parts, kind=DIST_F32,
-                  rerank=0):
+                  rerank=0, hop2_parts=None):
     """Alg. 4 where graph part i switches to ef2_parts[i] after switch_hop
-    expansions (the beam widths a predictor chose)."""
+    expansions (the beam widths a predictor chose), or, with hop2_parts,
+    stops after hop2_parts[i] further expansions (the stopping steps)."""
     q = np.ascontiguousarray(q, np.float32)
     ids = np.zeros(k, np.int64)
     dists = np.zeros(k, np.float32)
     stats = np.zeros(8, np.int64)
     e2 = np.ascontiguousarray(ef2_parts, np.int32)
+    h2 = None if hop2_parts is None else np.ascontiguousarray(hop2_parts, np.int64)
     st = lib().oracle_query_sw(ix.cstruct(), _p(q), lq, rq, k, ef_max, ef_max, -1, kind, rerank,
-                               switch_hop, _p(e2), _p(ids), _p(dists), _p(stats))
+                               switch_hop, _p(e2), _p(h2), _p(ids), _p(dists), _p(stats))
     return ids, dists, stats, st
 
 

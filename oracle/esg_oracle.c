@@ -309,12 +309,13 @@ static cand list_pop_min(sorted_list* l) {
  * w_query and n_parts describe the whole query; k is the answer size. */
 typedef struct {
   int64_t switch_hop;
-  int32_t ef2;
+  int32_t ef2;       /* > 0: new beam width */
   int32_t k;
   int64_t w_query;
   int32_t n_parts;
   int32_t pad_;
   double* feat;
+  int64_t hop2;      /* > 0: at most hop2 further expansions (stopping step) */
 } oracle_switch;
 
 static void probe_features(const oracle_switch* sw, const sorted_list* P, const sorted_list* Q,
@@ -394,6 +395,8 @@ int32_t oracle_search_part_sw(const oracle_index* ix, int32_t depth, int64_t hea
     if (sw && sw->switch_hop >= 0 && h == sw->switch_hop) {
       if (sw->feat)
         probe_features(sw, &P, &Q, cap_p, a, b, x, y, (double)e.dist, n_inr, nv, sw->feat);
+      if (sw->hop2 > 0 && (hop_budget < 0 || h + sw->hop2 < hop_budget))
+        hop_budget = h + sw->hop2;                     /* stopping step */
       if (sw->ef2 > 0) {                               /* keep the ef2 best of P and Q */
         if (P.len > sw->ef2) P.len = sw->ef2;
         if (Q.len > sw->ef2) Q.len = sw->ef2;
@@ -472,20 +475,20 @@ int32_t oracle_scan_part(const oracle_index* ix, int64_t x, int64_t y, const flo
 int32_t oracle_query_sw(const oracle_index* ix, const float* q, int64_t lq, int64_t rq,
                         int32_t k, int32_t ef, int64_t cap_p, int64_t hop_budget,
                         int32_t kind, int32_t rerank, int64_t switch_hop, const int32_t* ef2,
-                        int64_t* ids, float* dists, int64_t* stats);
+                        const int64_t* hop2, int64_t* ids, float* dists, int64_t* stats);
 
 int32_t oracle_query(const oracle_index* ix, const float* q, int64_t lq, int64_t rq,
                      int32_t k, int32_t ef, int64_t cap_p, int64_t hop_budget,
                      int32_t kind, int32_t rerank, int64_t* ids, float* dists,
                      int64_t* stats) {
-  return oracle_query_sw(ix, q, lq, rq, k, ef, cap_p, hop_budget, kind, rerank, -1, NULL, ids,
-                         dists, stats);
+  return oracle_query_sw(ix, q, lq, rq, k, ef, cap_p, hop_budget, kind, rerank, -1, NULL, NULL,
+                         ids, dists, stats);
 }
 
 int32_t oracle_query_sw(const oracle_index* ix, const float* q, int64_t lq, int64_t rq,
                         int32_t k, int32_t ef, int64_t cap_p, int64_t hop_budget,
                         int32_t kind, int32_t rerank, int64_t switch_hop, const int32_t* ef2,
-                        int64_t* ids, float* dists, int64_t* stats) {
+                        const int64_t* hop2, int64_t* ids, float* dists, int64_t* stats) {
   for (int32_t i = 0; i < k; i++) {
     ids[i] = -1;
     dists[i] = INFINITY;
@@ -511,10 +514,11 @@ int32_t oracle_query_sw(const oracle_index* ix, const float* q, int64_t lq, int6
       if (stats) { stats[2] += o[6] - o[5] + 1; stats[4]++; }
     } else {
       int64_t nv = 0, h = 0;
-      oracle_switch sw = {switch_hop, ef2 ? ef2[i] : 0, k, rq - lq + 1, np, 0, NULL};
+      oracle_switch sw = {switch_hop, ef2 ? ef2[i] : 0, k, rq - lq + 1, np, 0, NULL,
+                          hop2 ? hop2[i] : 0};
       st = oracle_search_part_sw(ix, (int32_t)o[1], o[2], o[3], o[4], o[5], o[6], q, ef,
                                  cap_p, hop_budget, kind, pd, pp, &len, NULL, 0, &nv, &h,
-                                 (switch_hop >= 0 && ef2) ? &sw : NULL);
+                                 (switch_hop >= 0 && (ef2 || hop2)) ? &sw : NULL);
       if (stats) { stats[1] += h; stats[2] += nv; stats[3]++; }
       if (st == OR_OK && rerank && kind != DIST_F32) {
         sorted_list R;

@@ -68,7 +68,8 @@ class SearchOpts(ctypes.Structure):
                 ("hop_budget", ctypes.c_int64), ("router_threshold", ctypes.c_int64),
                 ("use_graph", ctypes.c_int32), ("scan_rerank", ctypes.c_int32),
                 ("mlp", ctypes.c_void_p), ("probe_hops", ctypes.c_int32),
-                ("mlp_delta", ctypes.c_float), ("feat_out", ctypes.c_void_p),
+                ("mlp_delta", ctypes.c_float), ("mlp_target", ctypes.c_int32),
+                ("feat_out", ctypes.c_void_p),
                 ("trace", ctypes.c_void_p),
                 ("visited", ctypes.c_void_p), ("visited_cap", ctypes.c_int64),
                 ("n_invalid", ctypes.c_void_p)]
@@ -231,7 +232,7 @@ class Index:
                   rerank: bool = False, cand_cap: int = 0, hash_cap: int = 0,
                   hop_budget: int = -1, router_threshold: int = 0, use_graph: bool = False,
                   scan_rerank: int = 0, mlp=None, probe_hops: int = 0, mlp_delta: float = 0.0,
-                  feat_out=None, trace=None, visited=None, visited_cap: int = 0,
+                  mlp_target: int = 0, feat_out=None, trace=None, visited=None, visited_cap: int = 0,
                   n_invalid=None, ids=None, dists=None, stream=None, opts="build"):
         import torch
         nq = queries.shape[0]
@@ -252,6 +253,7 @@ class Index:
             o = SearchOpts(TRAV[traversal], int(rerank), cand_cap, hash_cap, hop_budget,
                            router_threshold, int(use_graph), scan_rerank,
                            None if mlp is None else mlp.data_ptr(), probe_hops, mlp_delta,
+                           mlp_target,
                            None if feat_out is None else feat_out.data_ptr(),
                            None if trace is None else trace.data_ptr(),
                            None if visited is None else visited.data_ptr(),

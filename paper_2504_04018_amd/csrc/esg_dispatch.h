@@ -10,7 +10,7 @@ constexpr int kNumScanWidths = 3;  // scan candidate lists of 64, 128, 256 keys
 
 struct KernelTable {
   int dim;
-  const void* fn[kNumKinds][kNumWidths];
+  const void* fn[kNumKinds][kNumWidths][2];   // [.][.][1]: with the learned switch
   const void* mfma;                       // MFMA approximate distances
   const void* select[kNumScanWidths];     // per-window top list
   const void* rerank[kNumScanWidths];     // merge + float32 rerank + certificate

@@ -65,7 +65,8 @@ struct SearchArgs {
   const float* mlp;       // parameters (kMlpParams floats) or null
   float* feat_out;        // [nq][2][kFeatStride] features, raw output and ef' (optional)
   int32_t probe_hops;
-  float mlp_delta;        // calibration offset added to the predicted log2(ef)
+  float mlp_delta;        // calibration offset added to the predicted log2 value
+  int32_t mlp_target;     // 0: the output sets the beam width, 1: the remaining hops
   const int32_t* qlist;   // queries to process (null = 0..nq-1)
   const int32_t* qcount;  // device count of qlist (null = nq)
   int32_t hash_cap;       // 16-bit LDS visited slots per wave (power of two)

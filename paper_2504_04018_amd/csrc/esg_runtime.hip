@@ -815,7 +815,8 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
     if (mr < k || mr > cap - 1) return ESG_EINVAL;
   }
 
-  const void* fn = idx->kt->fn[o.traversal][width_index(std::max(ef, cand_cap))];
+  const bool learn = (o.mlp || o.feat_out) && o.probe_hops > 0;   // kernel with the switch
+  const void* fn = idx->kt->fn[o.traversal][width_index(std::max(ef, cand_cap))][learn ? 1 : 0];
   if (!fn) return ESG_EUNSUPPORTED;
 
   esgk::SearchArgs a;
@@ -859,6 +860,8 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   a.feat_out = o.feat_out;
   a.probe_hops = (o.mlp || o.feat_out) ? o.probe_hops : 0;
   a.mlp_delta = o.mlp_delta;
+  if (o.mlp_target < 0 || o.mlp_target > 1) return ESG_EINVAL;
+  a.mlp_target = o.mlp_target;
 
   if (hipSetDevice(idx->device) != hipSuccess) return ESG_EHIP;
   const size_t lds = (size_t)esgk::kWavesPerGroup * (esgk::kStageBytes + 2 * (size_t)hash_cap);

@@ -22,20 +22,27 @@ struct Shape {
   static constexpr int CPL = (C + G - 1) / G;
 };
 
-template <int KIND, int E>
+template <int KIND, int E, bool LEARN>
 const void* kernel_ptr() {
   using S = Shape<KIND>;
   using S32 = Shape<kF32>;
-  return reinterpret_cast<const void*>(&search_kernel<KIND, S::G, S::CPL, S32::G, S32::CPL, E>);
+  return reinterpret_cast<const void*>(
+      &search_kernel<KIND, S::G, S::CPL, S32::G, S32::CPL, E, LEARN>);
+}
+
+template <int KIND, bool LEARN>
+void fill_one(KernelTable* t) {
+  t->fn[KIND][0][LEARN] = kernel_ptr<KIND, 1, LEARN>();
+  t->fn[KIND][1][LEARN] = kernel_ptr<KIND, 2, LEARN>();
+  t->fn[KIND][2][LEARN] = kernel_ptr<KIND, 4, LEARN>();
+  t->fn[KIND][3][LEARN] = kernel_ptr<KIND, 8, LEARN>();
+  t->fn[KIND][4][LEARN] = kernel_ptr<KIND, 16, LEARN>();
 }
 
 template <int KIND>
 void fill(KernelTable* t) {
-  t->fn[KIND][0] = kernel_ptr<KIND, 1>();
-  t->fn[KIND][1] = kernel_ptr<KIND, 2>();
-  t->fn[KIND][2] = kernel_ptr<KIND, 4>();
-  t->fn[KIND][3] = kernel_ptr<KIND, 8>();
-  t->fn[KIND][4] = kernel_ptr<KIND, 16>();
+  fill_one<KIND, false>(t);
+  fill_one<KIND, true>(t);
 }
 
 template <int E>

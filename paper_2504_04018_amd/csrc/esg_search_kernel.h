@@ -21,20 +21,23 @@ struct ProbeCtx {
   float* feat;       // where to write the features (or null)
 };
 
-// 12 -> 64 -> 64 -> 1 ReLU network, one hidden unit per lane; returns the
-// raw output on every lane.
-__device__ __forceinline__ float mlp_infer(const float* P, const float (&f)[kFeat], WaveLds* Ls,
+// 12 -> 64 -> 64 -> 1 ReLU network, one hidden unit per lane.  Lane i < 12
+// holds feature i in `f`; returns the raw output on every lane.  Inputs and
+// activations pass through the wave's LDS staging so that few registers are
+// live on top of the search state.
+__device__ __forceinline__ float mlp_infer(const float* __restrict__ P, float f, WaveLds* Ls,
                                            int lane) {
-  float x[kFeat];
-#pragma unroll
-  for (int i = 0; i < kFeat; i++) x[i] = (f[i] - P[kOffMu + i]) / P[kOffSd + i];
+  Ls->fstage[lane] = lane < kFeat ? (f - P[kOffMu + lane]) / P[kOffSd + lane] : 0.0f;
+  wave_lds_sync();
   float h1 = P[kOffB1 + lane];
-#pragma unroll
-  for (int i = 0; i < kFeat; i++) h1 = __builtin_fmaf(P[kOffW1 + lane * kFeat + i], x[i], h1);
+#pragma unroll 4
+  for (int i = 0; i < kFeat; i++) h1 = __builtin_fmaf(P[kOffW1 + lane * kFeat + i], Ls->fstage[i], h1);
   h1 = h1 > 0.0f ? h1 : 0.0f;
+  wave_lds_sync();
   Ls->fstage[lane] = h1;
   wave_lds_sync();
   float h2 = P[kOffB2 + lane];
+#pragma unroll 4
   for (int i = 0; i < kHidden; i++)
     h2 = __builtin_fmaf(P[kOffW2 + lane * kHidden + i], Ls->fstage[i], h2);
   h2 = h2 > 0.0f ? h2 : 0.0f;
@@ -45,7 +48,38 @@ __device__ __forceinline__ float mlp_infer(const float* P, const float (&f)[kFea
   return y + P[kOffB3];
 }
 
-template <int KIND, int G, int CPL, int E>
+// Feature `lane` (lanes 0..11) of a graph part after the probe, from the
+// wave-uniform state: log2 of the part's filter width and node size, their
+// ratio, log2 of the query width, number of parts - 1, fill of P and of Q
+// (relative to k, at most 4), in-range share of the visited points, the
+// best and k-th distances in Q and the best distance in P relative to the
+// entry's (or to the k-th), log2(1 + visited).
+__device__ __forceinline__ float probe_feature(int lane, float wp, float L, int64_t w_query,
+                                               int n_parts, int psize, int cap_p, int qsize,
+                                               int k, int64_t n_inr, int64_t nvis, float q0,
+                                               float qk, float p0, float den) {
+  const float lg_arg = lane == 0 ? wp : lane == 1 ? L : lane == 3 ? (float)w_query
+                                   : 1.0f + (float)nvis;
+  const float lg = __log2f(lg_arg);
+  float num = 1.0f, dv = 1.0f;
+  switch (lane) {
+    case 2: num = wp; dv = L; break;
+    case 5: num = (float)psize; dv = (float)cap_p; break;
+    case 6: num = (float)qsize; dv = (float)k; break;
+    case 7: num = (float)n_inr; dv = (float)nvis; break;
+    case 8: num = q0; dv = den; break;
+    case 9: num = qk; dv = den; break;
+    case 10: num = qk > 0.0f ? p0 : 1.0f; dv = qk > 0.0f ? qk : 1.0f; break;
+    default: break;
+  }
+  float f = num / dv;
+  if (lane == 6) f = fminf(f, 4.0f);
+  if (lane == 0 || lane == 1 || lane == 3 || lane == 11) f = lg;
+  if (lane == 4) f = (float)(n_parts - 1);
+  return f;
+}
+
+template <int KIND, int G, int CPL, int E, bool LEARN>
 __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* Ls, Visited& V,
                                                   const Part& pt, int m, int cap_p,
                                                   const float (&qr)[CPL][Traits<KIND>::W],
@@ -70,47 +104,113 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
   int64_t nvis = 1, hops = 0;
   int64_t n_inr = (ep >= pt.x && ep <= pt.y) ? 1 : 0;   // visited points inside [x,y]
   const float d_ep = key_dist(kep);
-  const bool learned = A.probe_hops > 0;
+  int64_t hop_limit = A.hop_budget;                         // < 0: unbounded
 
   // The row of the next candidate is fetched as soon as that candidate is
   // known (right after the new batch is sorted), so the load overlaps the
   // merges of the current expansion.
   uint64_t u = readlane64(P[0], 0);
   uint32_t vrow = lane < A.R ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
-  for (;;) {
-    if (u == kKeyInf) break;                                   // P is empty
-    if (learned && hops == A.probe_hops) {
-      // probe over: features -> predicted beam width for the rest
-      int qsize = 0, psize = 0;
-#pragma unroll
-      for (int e = 0; e < E; e++) {
-        qsize += __popcll(ballot(Q[e] != kKeyInf));
-        psize += __popcll(ballot(P[e] != kKeyInf));
+  auto expand = [&](bool probe_phase) {
+    for (;;) {
+      if (u == kKeyInf) break;                                   // P is empty
+      if (probe_phase && hops == A.probe_hops) break;           // probe over: switch first
+      const uint64_t worst = list_at(Q, m - 1);
+      if (worst != kKeyInf && worst < u) break;                  // farther than a full Q
+      if (hop_limit >= 0 && hops >= hop_limit) break;
+      list_pop(P, lane);
+      hops++;
+
+      const uint32_t v = vrow;
+      const bool is_new = visit(A, V, v, v != kNoNode && v >= pt.a && v <= pt.b, lane);
+      const uint64_t nm = ballot(is_new);
+      const int n_new = __popcll(nm);
+      if (n_new == 0) {
+        u = readlane64(P[0], 0);
+        vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
+        continue;
       }
-      const int kk = A.k < qsize ? A.k : qsize;
-      const float q0 = qsize > 0 ? key_dist(list_at(Q, 0)) : d_ep;
-      const float qk = kk > 0 ? key_dist(list_at(Q, kk - 1)) : d_ep;
-      const float p0 = key_dist(u);
-      const float wp = (float)(pt.y - pt.x + 1), L = (float)(pt.b - pt.a + 1);
-      const float den = d_ep > 0.0f ? d_ep : 1.0f;
-      float f[kFeat];
-      f[0] = __log2f(wp);
-      f[1] = __log2f(L);
-      f[2] = wp / L;
-      f[3] = __log2f((float)pc.w_query);
-      f[4] = (float)(pc.n_parts - 1);
-      f[5] = (float)psize / (float)cap_p;
-      f[6] = fminf((float)qsize / (float)A.k, 4.0f);
-      f[7] = (float)n_inr / (float)nvis;
-      f[8] = q0 / den;
-      f[9] = qk / den;
-      f[10] = qk > 0.0f ? p0 / qk : 1.0f;
-      f[11] = __log2f(1.0f + (float)nvis);
-      float y = 0.0f;
-      int efp = m;
-      if (A.mlp) {
-        y = mlp_infer(A.mlp, f, Ls, lane);
-        const float e2 = exp2f(y + A.mlp_delta);
+      if (is_new) Ls->ids[rank_below(nm)] = v;
+      wave_lds_sync();
+      const uint32_t nid = lane < n_new ? Ls->ids[lane] : kNoNode;
+      if (dump && lane < n_new && nvis + lane < A.visited_cap) dump[nvis + lane] = nid;
+      nvis += n_new;
+      n_inr += __popcll(ballot(lane < n_new && nid >= pt.x && nid <= pt.y));
+
+      const float bd = batch_dist<KIND, G, CPL>(A, nid, n_new, qr, Ls, lane);
+      uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
+      // A key that loses to a full Q can neither enter Q nor ever be expanded
+      // (the bound only tightens), so dropping it leaves P's useful part, Q
+      // and every later step unchanged.
+      if (worst != kKeyInf && worst < key) key = kKeyInf;
+      const uint64_t sm = ballot(key != kKeyInf);
+      const uint64_t p0 = readlane64(P[0], 0);
+      if (sm == 0) {
+        u = p0;
+        vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
+        continue;
+      }
+      if (__popcll(sm) <= kInsertMax) {
+        // few survivors: insert them one by one
+        uint64_t bmin = kKeyInf;
+        for (uint64_t mm = sm; mm; mm &= mm - 1) bmin = kmin(bmin, readlane64(key, __builtin_ctzll(mm)));
+        u = kmin(p0, bmin);
+        vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
+        for (uint64_t mm = sm; mm; mm &= mm - 1) {
+          const uint64_t kj = readlane64(key, __builtin_ctzll(mm));
+          list_insert(P, kj, cap_p, lane);
+          const uint32_t pj = key_pos(kj);
+          if (pj >= pt.x && pj <= pt.y) list_insert(Q, kj, m, lane);
+        }
+        continue;
+      }
+      key = sort32(key, lane);
+      const uint64_t kmin0 = readlane64(key, 0);
+      u = kmin(p0, kmin0);                                       // min of P after the merge
+      vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
+      list_merge32(P, bperm64(key, 63 - lane), cap_p, lane);
+      const uint32_t kp = key_pos(key);
+      const bool inr = lane < kBatch && key != kKeyInf && kp >= pt.x && kp <= pt.y;
+      const uint64_t qm = ballot(inr);
+      if (qm != 0) {
+        Ls->stage[lane] = kKeyInf;
+        wave_lds_sync();
+        if (inr) Ls->stage[63 - rank_below(qm)] = key;
+        wave_lds_sync();
+        list_merge32(Q, Ls->stage[lane], m, lane);
+      }
+    }
+  };
+  // The learned kernel runs the probe and the rest of the search as two
+  // copies of the loop, with the switch between them (no switch code
+  // inside a loop keeps register pressure at the plain kernel's level).
+  expand(LEARN);
+if (LEARN && u != kKeyInf && hops == A.probe_hops) {
+    // probe over: features -> predicted beam width or stopping step
+    int qsize = 0, psize = 0;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      qsize += __popcll(ballot(Q[e] != kKeyInf));
+      psize += __popcll(ballot(P[e] != kKeyInf));
+    }
+    const int kk = A.k < qsize ? A.k : qsize;
+    const float q0 = qsize > 0 ? key_dist(list_at(Q, 0)) : d_ep;
+    const float qk = kk > 0 ? key_dist(list_at(Q, kk - 1)) : d_ep;
+    const float f = probe_feature(lane, (float)(pt.y - pt.x + 1), (float)(pt.b - pt.a + 1),
+                                  pc.w_query, pc.n_parts, psize, cap_p, qsize, A.k, n_inr,
+                                  nvis, q0, qk, key_dist(u), d_ep > 0.0f ? d_ep : 1.0f);
+    float y = 0.0f;
+    int efp = m;
+    if (A.mlp) {
+      y = mlp_infer(A.mlp, f, Ls, lane);
+      const float e2 = exp2f(y + A.mlp_delta);
+      if (A.mlp_target == 1) {
+        // stopping step: the part may take ceil(2^(y + delta)) more expansions
+        const int64_t more = e2 >= 1.0e9f ? (int64_t)1000000000
+                                          : (int64_t)ceilf(e2 < 1.0f ? 1.0f : e2);
+        if (hop_limit < 0 || hops + more < hop_limit) hop_limit = hops + more;
+        efp = (int)more;
+      } else {
         efp = e2 >= (float)m ? m : (int)ceilf(e2);
         efp = efp < A.k ? A.k : efp;
         // continue with m = cand_cap = ef': keep the ef' best of P and Q
@@ -124,77 +224,15 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
         cap_p = efp;
         u = readlane64(P[0], 0);
       }
-      if (pc.feat && lane == 0) {
-#pragma unroll
-        for (int i = 0; i < kFeat; i++) pc.feat[i] = f[i];
+    }
+    if (pc.feat) {
+      if (lane < kFeat) pc.feat[lane] = f;
+      if (lane == 0) {
         pc.feat[kFeat] = y;
         pc.feat[kFeat + 1] = (float)efp;
       }
     }
-    const uint64_t worst = list_at(Q, m - 1);
-    if (worst != kKeyInf && worst < u) break;                  // farther than a full Q
-    if (A.hop_budget >= 0 && hops >= A.hop_budget) break;
-    list_pop(P, lane);
-    hops++;
-
-    const uint32_t v = vrow;
-    const bool is_new = visit(A, V, v, v != kNoNode && v >= pt.a && v <= pt.b, lane);
-    const uint64_t nm = ballot(is_new);
-    const int n_new = __popcll(nm);
-    if (n_new == 0) {
-      u = readlane64(P[0], 0);
-      vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
-      continue;
-    }
-    if (is_new) Ls->ids[rank_below(nm)] = v;
-    wave_lds_sync();
-    const uint32_t nid = lane < n_new ? Ls->ids[lane] : kNoNode;
-    if (dump && lane < n_new && nvis + lane < A.visited_cap) dump[nvis + lane] = nid;
-    nvis += n_new;
-    n_inr += __popcll(ballot(lane < n_new && nid >= pt.x && nid <= pt.y));
-
-    const float bd = batch_dist<KIND, G, CPL>(A, nid, n_new, qr, Ls, lane);
-    uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
-    // A key that loses to a full Q can neither enter Q nor ever be expanded
-    // (the bound only tightens), so dropping it leaves P's useful part, Q
-    // and every later step unchanged.
-    if (worst != kKeyInf && worst < key) key = kKeyInf;
-    const uint64_t sm = ballot(key != kKeyInf);
-    const uint64_t p0 = readlane64(P[0], 0);
-    if (sm == 0) {
-      u = p0;
-      vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
-      continue;
-    }
-    if (__popcll(sm) <= kInsertMax) {
-      // few survivors: insert them one by one
-      uint64_t bmin = kKeyInf;
-      for (uint64_t mm = sm; mm; mm &= mm - 1) bmin = kmin(bmin, readlane64(key, __builtin_ctzll(mm)));
-      u = kmin(p0, bmin);
-      vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
-      for (uint64_t mm = sm; mm; mm &= mm - 1) {
-        const uint64_t kj = readlane64(key, __builtin_ctzll(mm));
-        list_insert(P, kj, cap_p, lane);
-        const uint32_t pj = key_pos(kj);
-        if (pj >= pt.x && pj <= pt.y) list_insert(Q, kj, m, lane);
-      }
-      continue;
-    }
-    key = sort32(key, lane);
-    const uint64_t kmin0 = readlane64(key, 0);
-    u = kmin(p0, kmin0);                                       // min of P after the merge
-    vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
-    list_merge32(P, bperm64(key, 63 - lane), cap_p, lane);
-    const uint32_t kp = key_pos(key);
-    const bool inr = lane < kBatch && key != kKeyInf && kp >= pt.x && kp <= pt.y;
-    const uint64_t qm = ballot(inr);
-    if (qm != 0) {
-      Ls->stage[lane] = kKeyInf;
-      wave_lds_sync();
-      if (inr) Ls->stage[63 - rank_below(qm)] = key;
-      wave_lds_sync();
-      list_merge32(Q, Ls->stage[lane], m, lane);
-    }
+    expand(false);
   }
   return {hops, nvis};
 }
@@ -250,7 +288,7 @@ __device__ __forceinline__ void rerank_f32(const SearchArgs& A, WaveLds* Ls, int
   for (int e = 0; e < E; e++) Q[e] = R[e];
 }
 
-template <int KIND, int G, int CPL, int G32, int CPL32, int E>
+template <int KIND, int G, int CPL, int G32, int CPL32, int E, bool LEARN>
 __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, Visited& V,
                                               int64_t qi, int lane) {
   const int k = A.k;
@@ -298,7 +336,7 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
       pc.w_query = rq - lq + 1;
       pc.n_parts = np;
       pc.feat = A.feat_out ? A.feat_out + (qi * 2 + p) * kFeatStride : nullptr;
-      st = search_graph<KIND, G, CPL, E>(A, Ls, V, pt, m, cap_p, qr, Qp, dump, lane, pc);
+      st = search_graph<KIND, G, CPL, E, LEARN>(A, Ls, V, pt, m, cap_p, qr, Qp, dump, lane, pc);
       if constexpr (KIND != kF32)
         if (A.rerank) rerank_f32<G32, CPL32, E>(A, Ls, k, qr32, Qp, lane);
 #pragma unroll
@@ -332,8 +370,20 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
   }
 }
 
-template <int KIND, int G, int CPL, int G32, int CPL32, int E>
-__global__ __launch_bounds__(256) void search_kernel(SearchArgs A) {
+// Learned kernels with short lists are held to 4 waves per SIMD (the plain
+// kernel's occupancy): the few spills this costs sit mostly outside the
+// expansion loop and are cheaper than a lost wave.
+#ifndef ESG_PLAIN_MIN_WAVES
+#define ESG_PLAIN_MIN_WAVES 1
+#endif
+template <int KIND, int E, bool LEARN>
+constexpr int min_waves() {
+  return (E <= 2 && KIND != kFP8) ? (LEARN ? 4 : ESG_PLAIN_MIN_WAVES) : 1;
+}
+
+template <int KIND, int G, int CPL, int G32, int CPL32, int E, bool LEARN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<KIND, E, LEARN>(), 8)))
+void search_kernel(SearchArgs A) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int lane = lane_id();
   const int wid = (int)(threadIdx.x >> 6);
@@ -353,7 +403,7 @@ __global__ __launch_bounds__(256) void search_kernel(SearchArgs A) {
     const int64_t ti = (int64_t)readlane(t, 0);
     if (ti >= count) break;
     const int64_t qi = A.qlist ? (int64_t)A.qlist[ti] : ti;
-    process_query<KIND, G, CPL, G32, CPL32, E>(A, Ls, V, qi, lane);
+    process_query<KIND, G, CPL, G32, CPL32, E, LEARN>(A, Ls, V, qi, lane);
   }
 }
 

@@ -134,3 +134,45 @@ def test_learned_search_parity(tiny, delta, probe):
         assert np.array_equal(ids[i], oid), i
         assert np.array_equal(dists[i].view(np.uint32), od.view(np.uint32)), i
     assert switched > 50
+
+
+@pytest.mark.parametrize("delta,probe", [(0.0, 4), (2.0, 8)])
+def test_learned_stop_parity(tiny, delta, probe):
+    """Stopping-step target: every switched part takes at most the granted
+    expansions after the probe, and the oracle, given those grants,
+    reproduces ids, distances and per-part hop counts."""
+    w, gix, oix = tiny
+    rng = np.random.default_rng(4)
+    p = random_params(rng, 0.15)
+    p[5057:5069] = [10, 10, 0.5, 11, 0.5, 0.5, 2, 0.5, 0.5, 1, 1, 8]
+    p[5069:] = [3, 3, 0.3, 3, 0.5, 0.3, 1.5, 0.3, 0.3, 0.5, 0.5, 2]
+    p[5056] = 3.0                                # bias: about 8 more expansions
+    nq = len(w["Q"])
+    Q, l, r = w["Q"], w["l"], w["r"]
+    feat = torch.full((nq, 2, 16), float("nan"), device=DEV)
+    tr = esg.trace_tensor(nq, DEV)
+    ef, k = 64, 10
+    ids, dists = gix.search_ex(_t(Q), _t(l), _t(r), k, ef, mlp=_t(p), probe_hops=probe,
+                               mlp_delta=delta, mlp_target=1, feat_out=feat, trace=tr)
+    torch.cuda.synchronize()
+    F = feat.cpu().numpy()
+    T = esg.decode_trace(tr)
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    switched = cut = 0
+    for i in range(nq):
+        parts, npart = oracle.select(oix.n, oix.leaf, int(l[i]), int(r[i]))
+        hop2 = np.zeros(2, np.int64)
+        for j, pt in enumerate(parts):
+            if pt["kind"] != oracle.KIND_GRAPH or np.isnan(F[i, j, 0]):
+                continue
+            switched += 1
+            hop2[j] = int(F[i, j, 13])
+            assert hop2[j] >= 1
+            assert T["hops"][i, j] <= probe + hop2[j]
+            cut += int(T["hops"][i, j] == probe + hop2[j])
+        oid, od, ost, st = oracle.query_learned(oix, Q[i], int(l[i]), int(r[i]), k, ef, probe,
+                                                np.zeros(2, np.int32), hop2_parts=hop2)
+        assert st == 0
+        assert np.array_equal(ids[i], oid), i
+        assert np.array_equal(dists[i].view(np.uint32), od.view(np.uint32)), i
+    assert switched > 50 and cut > 10

@@ -400,6 +400,38 @@ def test_query_merges_parts():
     assert seen2 > 0
 
 
+@pytest.mark.parametrize("seed", range(2))
+def test_learned_switch_special_cases(seed):
+    """The learned switch reduces to plain Alg. 1 in three special cases:
+    a new beam equal to the old one changes nothing; a switch at hop 0 to
+    beam e is the search with ef = e from the start; granting G further
+    expansions after s hops is the per-part hop budget s + G."""
+    rng = np.random.default_rng(20 + seed)
+    X = rng.standard_normal((600, 8)).astype(np.float32)
+    ix = make_test_index(X, leaf=12, R=6, ep_mode="random", rng=rng)
+    cut = 0
+    for _ in range(50):
+        l = int(rng.integers(0, 600))
+        r = int(rng.integers(l, 600))
+        q = rng.standard_normal(8).astype(np.float32)
+        k, ef, s = 5, 24, int(rng.integers(1, 6))
+        base = oracle.query(ix, q, l, r, k, ef)
+        same = oracle.query_learned(ix, q, l, r, k, ef, s, np.array([ef, ef], np.int32))
+        assert same[0].tolist() == base[0].tolist() and same[1].tolist() == base[1].tolist()
+        assert same[2][1] == base[2][1]
+        e = int(rng.integers(k, ef))
+        small = oracle.query(ix, q, l, r, k, e)
+        sw0 = oracle.query_learned(ix, q, l, r, k, ef, 0, np.array([e, e], np.int32))
+        assert sw0[0].tolist() == small[0].tolist() and sw0[2][1] == small[2][1]
+        g = int(rng.integers(1, 8))
+        budget = oracle.query(ix, q, l, r, k, ef, hop_budget=s + g)
+        stop = oracle.query_learned(ix, q, l, r, k, ef, s, np.zeros(2, np.int32),
+                                    hop2_parts=np.array([g, g]))
+        assert stop[0].tolist() == budget[0].tolist() and stop[2][1] == budget[2][1]
+        cut += budget[2][1] < base[2][1]
+    assert cut > 10
+
+
 # ---------------------------------------------------------------- brute force
 
 def test_bruteforce_matches_sort_definition():
