@@ -190,7 +190,10 @@ typedef struct {
                             features of the search state to y and the part
                             continues with m = cand_cap = ef' =
                             clamp(ceil(2^(y + mlp_delta)), k, ef), keeping
-                            the ef' best of P and Q                       */
+                            the ef' best of P and Q.  Layout as for
+                            esg_mlp_forward; each call copies the weights
+                            into the index's own inference layout on the
+                            call's stream first (read-only here)          */
   int32_t probe_hops;    /* > 0 with mlp (or with feat_out alone: features
                             only, no change of beam)                       */
   float mlp_delta;       /* calibration offset added to y                   */

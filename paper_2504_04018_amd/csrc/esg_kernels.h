@@ -62,7 +62,7 @@ struct SearchArgs {
   uint32_t* counter;      // work-queue head
   // learned beam width: after probe_hops expansions at m = ef the MLP sets
   // m = cand_cap = ef' for the rest of the part
-  const float* mlp;       // parameters (kMlpParams floats) or null
+  const float* mlp;       // packed parameters (kMlpParams floats: W1, W2 input-major) or null
   float* feat_out;        // [nq][2][kFeatStride] features, raw output and ef' (optional)
   int32_t probe_hops;
   float mlp_delta;        // calibration offset added to the predicted log2 value

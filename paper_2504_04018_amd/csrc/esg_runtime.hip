@@ -70,6 +70,7 @@ struct esg_index {
   uint32_t* spill = nullptr;
   int64_t spill_words = 0, spill_slots = 0;
   uint32_t* counter = nullptr;
+  float* mlp_pack = nullptr;    // the predictor's weights in the search kernel's layout
   // brute-force scan: norms and rounding statistics of the bfloat16 copy
   float* norm2 = nullptr;
   float* stats = nullptr;       // [0] max |x|, [1] max relative bfloat16 rounding error
@@ -124,6 +125,24 @@ struct esg_index {
 namespace {
 
 __global__ void reset_counter_kernel(uint32_t* c) { *c = 0u; }
+
+// Predictor weights for inference: W1 and W2 regrouped as [input/4][hidden
+// unit][4] (each hidden unit's lane reads 16 consecutive bytes per step and
+// the wave one contiguous kilobyte); every other block is copied as is.
+__global__ void mlp_pack_kernel(const float* __restrict__ src, float* __restrict__ dst) {
+  using namespace esgk;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= kMlpParams) return;
+  int from = j;
+  if (j < kOffB1) {                       // W1: [c][h][e] <- W1[h][4c + e]
+    const int t = j - kOffW1, c = t / (4 * kHidden), h = (t / 4) % kHidden, e = t % 4;
+    from = kOffW1 + h * kFeat + 4 * c + e;
+  } else if (j >= kOffW2 && j < kOffB2) { // W2: [c][h][e] <- W2[h][4c + e]
+    const int t = j - kOffW2, c = t / (4 * kHidden), h = (t / 4) % kHidden, e = t % 4;
+    from = kOffW2 + h * kHidden + 4 * c + e;
+  }
+  dst[j] = src[from];
+}
 
 // float32 -> bfloat16, round to nearest even (finite inputs).
 __global__ void encode_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict__ y,
@@ -396,6 +415,7 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
   A((void**)&ix->ext_id, ids.size() * 8);
   A((void**)&ix->spill, (size_t)ix->spill_slots * ix->spill_words * 4);
   A((void**)&ix->counter, 256);
+  A((void**)&ix->mlp_pack, sizeof(float) * esgk::kMlpParams);
   if (st != ESG_OK) {
     ix->release();
     delete ix;
@@ -856,7 +876,7 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   a.counter = idx->counter;
   a.hash_cap = hash_cap;
   if (o.probe_hops < 0 || (o.mlp && o.probe_hops < 1)) return ESG_EINVAL;
-  a.mlp = o.mlp;
+  a.mlp = o.mlp ? idx->mlp_pack : nullptr;
   a.feat_out = o.feat_out;
   a.probe_hops = (o.mlp || o.feat_out) ? o.probe_hops : 0;
   a.mlp_delta = o.mlp_delta;
@@ -867,6 +887,10 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   const size_t lds = (size_t)esgk::kWavesPerGroup * (esgk::kStageBytes + 2 * (size_t)hash_cap);
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto sequence = [&](hipStream_t st) -> int32_t {
+    if (o.mlp) {
+      mlp_pack_kernel<<<(esgk::kMlpParams + 255) / 256, 256, 0, st>>>(o.mlp, idx->mlp_pack);
+      if (hipGetLastError() != hipSuccess) return ESG_EHIP;
+    }
     return o.router_threshold > 0 ? launch_routed(idx, a, fn, lds, o.router_threshold, mr, st)
                                   : launch_search(idx, a, fn, lds, nq, st);
   };

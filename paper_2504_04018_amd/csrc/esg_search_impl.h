@@ -129,14 +129,14 @@ __device__ __forceinline__ void load_query(const float* q, int d, int lane,
 
 // Distances of up to 32 vectors whose positions sit in lanes 0..n_new-1 of
 // `nid`.  Returns lane j's distance (j < n_new).
-template <int KIND, int G, int CPL>
+template <int KIND, int G, int CPL, int RFMAX = 8>
 __device__ __forceinline__ float batch_dist(const SearchArgs& A, uint32_t nid, int n_new,
                                             const float (&qr)[CPL][Traits<KIND>::W], WaveLds* L,
                                             int lane) {
   constexpr int W = Traits<KIND>::W;
   constexpr int VPG = (kWave / G) < kBatch ? (kWave / G) : kBatch;  // vectors per round
   constexpr int NR = (kBatch + VPG - 1) / VPG;                       // rounds for a full batch
-  constexpr int RF0 = 8 / CPL;
+  constexpr int RF0 = RFMAX / CPL;
   constexpr int RF = RF0 < 1 ? 1 : (RF0 > NR ? NR : RF0);            // rounds in flight
   const int grp = lane / G, t = lane % G;
   const int C = (A.d + W - 1) / W;
@@ -421,21 +421,23 @@ __device__ __forceinline__ Part to_part(const Desc& it, int64_t leaf) {
           (uint32_t)it.x, (uint32_t)it.y};
 }
 
-// Alg. 4: at most two parts for fanout 2 (Lemma 4.2).  Returns the count,
-// or -1 if the descent would emit more (never for a fanout-2 tree).
+// Alg. 4: at most two parts for fanout 2 (Lemma 4.2).  Returns the count
+// (or -1 if the descent would emit more: never for a fanout-2 tree) and part
+// `which` (0 or 1) in `out`.  The search recomputes the descent for each part
+// (a few scalar steps) so that no part record has to be kept in memory.
 __device__ __forceinline__ int select_parts(int64_t n, int64_t leaf, int32_t c_den, int64_t lq,
-                                            int64_t rq, Part& p0, Part& p1) {
+                                            int64_t rq, int which, Part& out) {
   Desc it = {0, n - 1, lq, rq, 1, 0}, right = it, dummy = it;
   bool split = false, s2 = false;
   if (!descend(it, leaf, c_den, true, right, split)) return -1;
   if (!split) {
-    p0 = to_part(it, leaf);
+    out = to_part(it, leaf);
     return 1;
   }
   if (!descend(it, leaf, c_den, false, dummy, s2)) return -1;
   if (!descend(right, leaf, c_den, false, dummy, s2)) return -1;
-  p0 = to_part(it, leaf);
-  p1 = to_part(right, leaf);
+  if (which == 1) it = right;
+  out = to_part(it, leaf);
   return 2;
 }
 

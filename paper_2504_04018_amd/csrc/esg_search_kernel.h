@@ -21,27 +21,59 @@ struct ProbeCtx {
   float* feat;       // where to write the features (or null)
 };
 
-// 12 -> 64 -> 64 -> 1 ReLU network, one hidden unit per lane.  Lane i < 12
-// holds feature i in `f`; returns the raw output on every lane.  Inputs and
-// activations pass through the wave's LDS staging so that few registers are
-// live on top of the search state.
+// 12 -> 64 -> 64 -> 1 ReLU network, one hidden unit per lane.  Weights in
+// the packed layout: W1 and W2 as [input/4][hidden unit][4], so each lane
+// reads its unit's weights 16 bytes at a time and a wave's read is one
+// contiguous kilobyte.  The loads are issued in five rounds (W1 with the
+// biases, then four quarters of W2): few round trips, few registers.
+// Lane i < 12 holds feature i in `f`; returns the raw output on every lane.
+// The normalised inputs and the first hidden layer pass through the wave's
+// LDS staging.
 __device__ __forceinline__ float mlp_infer(const float* __restrict__ P, float f, WaveLds* Ls,
                                            int lane) {
+  const float4* __restrict__ w1 = reinterpret_cast<const float4*>(P + kOffW1);
+  const float4* __restrict__ w2 = reinterpret_cast<const float4*>(P + kOffW2);
+  float4 a[kFeat / 4];
+#pragma unroll
+  for (int c = 0; c < kFeat / 4; c++) a[c] = w1[c * kHidden + lane];
+  float h1 = P[kOffB1 + lane];
+  const float b2 = P[kOffB2 + lane], w3 = P[kOffW3 + lane];
   Ls->fstage[lane] = lane < kFeat ? (f - P[kOffMu + lane]) / P[kOffSd + lane] : 0.0f;
   wave_lds_sync();
-  float h1 = P[kOffB1 + lane];
-#pragma unroll 4
-  for (int i = 0; i < kFeat; i++) h1 = __builtin_fmaf(P[kOffW1 + lane * kFeat + i], Ls->fstage[i], h1);
+  const float4* xs = reinterpret_cast<const float4*>(Ls->fstage);
+#pragma unroll
+  for (int c = 0; c < kFeat / 4; c++) {
+    const float4 x = xs[c];
+    h1 = __builtin_fmaf(a[c].x, x.x, h1);
+    h1 = __builtin_fmaf(a[c].y, x.y, h1);
+    h1 = __builtin_fmaf(a[c].z, x.z, h1);
+    h1 = __builtin_fmaf(a[c].w, x.w, h1);
+  }
   h1 = h1 > 0.0f ? h1 : 0.0f;
   wave_lds_sync();
   Ls->fstage[lane] = h1;
   wave_lds_sync();
-  float h2 = P[kOffB2 + lane];
-#pragma unroll 4
-  for (int i = 0; i < kHidden; i++)
-    h2 = __builtin_fmaf(P[kOffW2 + lane * kHidden + i], Ls->fstage[i], h2);
+  float h2 = b2;
+#pragma unroll
+  for (int half = 0; half < 4; half++) {
+    float4 b[kHidden / 16];
+    // the round's addresses depend on the previous round's sum, so the
+    // compiler cannot issue all rounds at once (that would need 64 VGPRs)
+    int col = lane;
+    asm volatile("" : "+v"(col) : "v"(h2));
+#pragma unroll
+    for (int c = 0; c < kHidden / 16; c++) b[c] = w2[(half * (kHidden / 16) + c) * kHidden + col];
+#pragma unroll
+    for (int c = 0; c < kHidden / 16; c++) {
+      const float4 x = xs[half * (kHidden / 16) + c];
+      h2 = __builtin_fmaf(b[c].x, x.x, h2);
+      h2 = __builtin_fmaf(b[c].y, x.y, h2);
+      h2 = __builtin_fmaf(b[c].z, x.z, h2);
+      h2 = __builtin_fmaf(b[c].w, x.w, h2);
+    }
+  }
   h2 = h2 > 0.0f ? h2 : 0.0f;
-  float y = P[kOffW3 + lane] * h2;
+  float y = w3 * h2;
 #pragma unroll
   for (int s = 1; s < kWave; s <<= 1) y = y + xor_f(y, s, lane);
   wave_lds_sync();
@@ -78,6 +110,11 @@ __device__ __forceinline__ float probe_feature(int lane, float wp, float L, int6
   if (lane == 4) f = (float)(n_parts - 1);
   return f;
 }
+
+// Gather rounds in flight per lane: the learned kernel keeps 4 instead of 8
+// to leave registers for the predictor.
+template <bool LEARN>
+constexpr int kLearnRF = LEARN ? 4 : 8;
 
 template <int KIND, int G, int CPL, int E, bool LEARN>
 __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* Ls, Visited& V,
@@ -137,7 +174,7 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
       nvis += n_new;
       n_inr += __popcll(ballot(lane < n_new && nid >= pt.x && nid <= pt.y));
 
-      const float bd = batch_dist<KIND, G, CPL>(A, nid, n_new, qr, Ls, lane);
+      const float bd = batch_dist<KIND, G, CPL, kLearnRF<LEARN>>(A, nid, n_new, qr, Ls, lane);
       uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
       // A key that loses to a full Q can neither enter Q nor ever be expanded
       // (the bound only tightens), so dropping it leaves P's useful part, Q
@@ -295,10 +332,9 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
   int64_t* ids = A.ids + qi * k;
   float* dists = A.dists + qi * k;
   const int64_t lq = A.l[qi], rq = A.r[qi];
-  Part parts[2];
-  int np = 0;
   const bool valid = lq >= 0 && rq < A.n && lq <= rq;
-  if (valid) np = select_parts(A.n, A.leaf, A.c_den, lq, rq, parts[0], parts[1]);
+  Part pt{};
+  const int np = valid ? select_parts(A.n, A.leaf, A.c_den, lq, rq, 0, pt) : 0;
   if (!valid || np < 0) {
     for (int i = lane; i < k; i += kWave) {
       ids[i] = -1;
@@ -319,10 +355,10 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
   const int cap_p = A.cand_cap;
   uint64_t Res[E];
   list_clear(Res);
-#pragma unroll
-  for (int p = 0; p < 2; p++) {
-    if (p >= np) break;
-    const Part pt = parts[p];
+  // One copy of the part code (not unrolled: half the instruction footprint).
+#pragma nounroll
+  for (int p = 0; p < np; p++) {
+    if (p == 1) select_parts(A.n, A.leaf, A.c_den, lq, rq, 1, pt);
     uint64_t Qp[E];
     PartStats st{0, 0};
     const uint64_t t_start = A.trace ? __builtin_amdgcn_s_memrealtime() : 0;
@@ -370,15 +406,13 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
   }
 }
 
-// Learned kernels with short lists are held to 4 waves per SIMD (the plain
-// kernel's occupancy): the few spills this costs sit mostly outside the
-// expansion loop and are cheaper than a lost wave.
-#ifndef ESG_PLAIN_MIN_WAVES
-#define ESG_PLAIN_MIN_WAVES 1
-#endif
+// Occupancy target: the float32 kernels with lists of up to 128 keys and the
+// bfloat16 kernels with 64 keys are held to 4 waves per SIMD (measured: the
+// few spills this costs are cheaper than a lost wave on these latency-bound
+// kernels); the others keep the compiler's choice.
 template <int KIND, int E, bool LEARN>
 constexpr int min_waves() {
-  return (E <= 2 && KIND != kFP8) ? (LEARN ? 4 : ESG_PLAIN_MIN_WAVES) : 1;
+  return ((KIND == kF32 && E <= 2) || (KIND == kBF16 && E == 1)) ? 4 : 1;
 }
 
 template <int KIND, int G, int CPL, int G32, int CPL32, int E, bool LEARN>
