@@ -24,56 +24,61 @@ struct ProbeCtx {
 // 12 -> 64 -> 64 -> 1 ReLU network, one hidden unit per lane.  Weights in
 // the packed layout: W1 and W2 as [input/4][hidden unit][4], so each lane
 // reads its unit's weights 16 bytes at a time and a wave's read is one
-// contiguous kilobyte.  The loads are issued in five rounds (W1 with the
-// biases, then four quarters of W2): few round trips, few registers.
-// Lane i < 12 holds feature i in `f`; returns the raw output on every lane.
-// The normalised inputs and the first hidden layer pass through the wave's
-// LDS staging.
+// contiguous kilobyte.  Loads go in rounds of kMlpRound float4 per lane;
+// each round's addresses depend on the previous round's sum, so the
+// compiler cannot issue them all at once: the network then adds few
+// registers on top of the live search state.  Lane i < 12 holds feature i
+// in `f`; returns the raw output on every lane.  The normalised inputs and
+// the first hidden layer pass through the wave's LDS staging.
+constexpr int kMlpRound = 2;
+
 __device__ __forceinline__ float mlp_infer(const float* __restrict__ P, float f, WaveLds* Ls,
                                            int lane) {
   const float4* __restrict__ w1 = reinterpret_cast<const float4*>(P + kOffW1);
   const float4* __restrict__ w2 = reinterpret_cast<const float4*>(P + kOffW2);
-  float4 a[kFeat / 4];
-#pragma unroll
-  for (int c = 0; c < kFeat / 4; c++) a[c] = w1[c * kHidden + lane];
-  float h1 = P[kOffB1 + lane];
-  const float b2 = P[kOffB2 + lane], w3 = P[kOffW3 + lane];
   Ls->fstage[lane] = lane < kFeat ? (f - P[kOffMu + lane]) / P[kOffSd + lane] : 0.0f;
   wave_lds_sync();
   const float4* xs = reinterpret_cast<const float4*>(Ls->fstage);
+  auto layer = [&](const float4* __restrict__ w, int n4, float acc) {
+    for (int r = 0; r < n4; r += kMlpRound) {
+      int col = lane;
+      asm volatile("" : "+v"(col) : "v"(acc));
+      float4 b[kMlpRound];
 #pragma unroll
-  for (int c = 0; c < kFeat / 4; c++) {
-    const float4 x = xs[c];
-    h1 = __builtin_fmaf(a[c].x, x.x, h1);
-    h1 = __builtin_fmaf(a[c].y, x.y, h1);
-    h1 = __builtin_fmaf(a[c].z, x.z, h1);
-    h1 = __builtin_fmaf(a[c].w, x.w, h1);
+      for (int c = 0; c < kMlpRound; c++) b[c] = w[(r + c) * kHidden + col];
+#pragma unroll
+      for (int c = 0; c < kMlpRound; c++) {
+        const float4 x = xs[r + c];
+        acc = __builtin_fmaf(b[c].x, x.x, acc);
+        acc = __builtin_fmaf(b[c].y, x.y, acc);
+        acc = __builtin_fmaf(b[c].z, x.z, acc);
+        acc = __builtin_fmaf(b[c].w, x.w, acc);
+      }
+    }
+    return acc > 0.0f ? acc : 0.0f;
+  };
+  static_assert(kFeat % 4 == 0 && (kFeat / 4) % 1 == 0, "feature count");
+  float h1 = 0.0f;
+  {
+    // W1: kFeat/4 = 3 float4 per lane, one at a time
+    float acc = P[kOffB1 + lane];
+    for (int c = 0; c < kFeat / 4; c++) {
+      int col = lane;
+      asm volatile("" : "+v"(col) : "v"(acc));
+      const float4 b = w1[c * kHidden + col];
+      const float4 x = xs[c];
+      acc = __builtin_fmaf(b.x, x.x, acc);
+      acc = __builtin_fmaf(b.y, x.y, acc);
+      acc = __builtin_fmaf(b.z, x.z, acc);
+      acc = __builtin_fmaf(b.w, x.w, acc);
+    }
+    h1 = acc > 0.0f ? acc : 0.0f;
   }
-  h1 = h1 > 0.0f ? h1 : 0.0f;
   wave_lds_sync();
   Ls->fstage[lane] = h1;
   wave_lds_sync();
-  float h2 = b2;
-#pragma unroll
-  for (int half = 0; half < 4; half++) {
-    float4 b[kHidden / 16];
-    // the round's addresses depend on the previous round's sum, so the
-    // compiler cannot issue all rounds at once (that would need 64 VGPRs)
-    int col = lane;
-    asm volatile("" : "+v"(col) : "v"(h2));
-#pragma unroll
-    for (int c = 0; c < kHidden / 16; c++) b[c] = w2[(half * (kHidden / 16) + c) * kHidden + col];
-#pragma unroll
-    for (int c = 0; c < kHidden / 16; c++) {
-      const float4 x = xs[half * (kHidden / 16) + c];
-      h2 = __builtin_fmaf(b[c].x, x.x, h2);
-      h2 = __builtin_fmaf(b[c].y, x.y, h2);
-      h2 = __builtin_fmaf(b[c].z, x.z, h2);
-      h2 = __builtin_fmaf(b[c].w, x.w, h2);
-    }
-  }
-  h2 = h2 > 0.0f ? h2 : 0.0f;
-  float y = w3 * h2;
+  const float h2 = layer(w2, kHidden / 4, P[kOffB2 + lane]);
+  float y = P[kOffW3 + lane] * h2;
 #pragma unroll
   for (int s = 1; s < kWave; s <<= 1) y = y + xor_f(y, s, lane);
   wave_lds_sync();
@@ -111,10 +116,14 @@ __device__ __forceinline__ float probe_feature(int lane, float wp, float L, int6
   return f;
 }
 
-// Gather rounds in flight per lane: the learned kernel keeps 4 instead of 8
-// to leave registers for the predictor.
-template <bool LEARN>
-constexpr int kLearnRF = LEARN ? 4 : 8;
+// Gather rounds in flight per lane: the learned kernels with narrow storage
+// keep 4 instead of 8 to leave registers for the predictor (measured: fewer
+// spills beat more loads in flight there; the float32 one keeps 8).
+#ifndef ESG_LEARN_RF
+#define ESG_LEARN_RF 4
+#endif
+template <int KIND, bool LEARN>
+constexpr int kLearnRF = LEARN ? (KIND == kF32 ? 8 : ESG_LEARN_RF) : 8;
 
 template <int KIND, int G, int CPL, int E, bool LEARN>
 __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* Ls, Visited& V,
@@ -174,7 +183,7 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
       nvis += n_new;
       n_inr += __popcll(ballot(lane < n_new && nid >= pt.x && nid <= pt.y));
 
-      const float bd = batch_dist<KIND, G, CPL, kLearnRF<LEARN>>(A, nid, n_new, qr, Ls, lane);
+      const float bd = batch_dist<KIND, G, CPL, kLearnRF<KIND, LEARN>>(A, nid, n_new, qr, Ls, lane);
       uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
       // A key that loses to a full Q can neither enter Q nor ever be expanded
       // (the bound only tightens), so dropping it leaves P's useful part, Q
@@ -348,8 +357,6 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
   const float* q = A.queries + qi * (int64_t)A.d;
   float qr[CPL][Traits<KIND>::W];
   load_query<KIND, G, CPL>(q, A.d, lane, qr);
-  float qr32[CPL32][4];
-  if constexpr (KIND != kF32) load_query<kF32, G32, CPL32>(q, A.d, lane, qr32);
 
   const int m = A.ef;
   const int cap_p = A.cand_cap;
@@ -364,7 +371,11 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
     const uint64_t t_start = A.trace ? __builtin_amdgcn_s_memrealtime() : 0;
     if (pt.kind == 2) {
       if constexpr (KIND == kF32) scan_leaf<G, CPL, E>(A, Ls, pt, k, qr, Qp, lane);
-      else scan_leaf<G32, CPL32, E>(A, Ls, pt, k, qr32, Qp, lane);
+      else {
+        float qr32[CPL32][4];               // loaded where needed, not kept across the search
+        load_query<kF32, G32, CPL32>(q, A.d, lane, qr32);
+        scan_leaf<G32, CPL32, E>(A, Ls, pt, k, qr32, Qp, lane);
+      }
       st.n_visited = (int64_t)(pt.y - pt.x) + 1;
     } else {
       uint32_t* dump = A.visited ? A.visited + (qi * 2 + p) * A.visited_cap : nullptr;
@@ -374,7 +385,11 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
       pc.feat = A.feat_out ? A.feat_out + (qi * 2 + p) * kFeatStride : nullptr;
       st = search_graph<KIND, G, CPL, E, LEARN>(A, Ls, V, pt, m, cap_p, qr, Qp, dump, lane, pc);
       if constexpr (KIND != kF32)
-        if (A.rerank) rerank_f32<G32, CPL32, E>(A, Ls, k, qr32, Qp, lane);
+        if (A.rerank) {
+          float qr32[CPL32][4];
+          load_query<kF32, G32, CPL32>(q, A.d, lane, qr32);
+          rerank_f32<G32, CPL32, E>(A, Ls, k, qr32, Qp, lane);
+        }
 #pragma unroll
       for (int e = 0; e < E; e++)
         if (e * kWave + lane >= k) Qp[e] = kKeyInf;
