@@ -39,7 +39,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TARGET_RECALL = 0.95
-EF_GRID = [10, 12, 14, 16, 18, 20, 22, 24, 28, 32, 40, 48, 64, 96, 128, 192, 256]
+EF_GRID = [10, 12, 14, 16, 18, 20, 22, 24, 28, 32, 40, 48, 64, 96, 100, 112, 128, 192, 256, 384, 512, 768, 1024]
 DELTA_GRID = [-1.0, -0.75, -0.5, -0.375, -0.25, -0.125, 0.0, 0.25, 0.5]
 LABEL_EF_GRID = [10, 12, 14, 16, 18, 20, 22, 24, 28, 32, 40, 48, 64, 96, 128, 192, 256]
 LABEL_HOP_GRID = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256]
@@ -54,7 +54,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="deep", choices=["deep", "sift"])
+    ap.add_argument("--workload", default="deep", choices=["deep", "sift", "embedding"],
+                    help="embedding: unit-norm d=768, k=100, fp8 storage (N defaults to 200,000)")
     ap.add_argument("--n", type=int, default=None, help="shrink N (default: the full workload)")
     ap.add_argument("--nq", type=int, default=None, help="shrink the query count")
     ap.add_argument("--ntrain", type=int, default=200_000, help="training traces")
@@ -147,7 +148,9 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
-    cid = 2 if args.workload == "deep" else 1
+    cid = {"deep": 2, "sift": 1, "embedding": 3}[args.workload]
+    if cid == 3 and args.n is None:
+        args.n = 200_000
     t0 = time.time()
     w = synth.make_workload(cid, n=args.n, nq=args.nq)
     n, d, k = w["n"], w["d"], w["k"]
@@ -162,9 +165,11 @@ def main():
                         leaf=w["leaf"], ef_construction=w["ef_construction"], verbose=True)
         os.replace(path + ".tmp", path)
         log(f"index built in {time.time() - t0:.1f}s")
-    del w["X"]
+    X = w.pop("X")                        # kept for the float64 distance check
     ix = esg.Index(path, 0)
     ix.add_storage("bf16")
+    if cid == 3:
+        ix.add_storage("fp8")
     ix.reserve(max(nq, args.ntrain), 262144)
     info = ix.info()
 
@@ -222,7 +227,8 @@ def main():
         base = dict(rerank=True, use_graph=True)
         tuned, _ = autotune.tune(
             ix, Q, l, r, k, plain_best["ef"], base, recall, 0.0,
-            grid={"traversal": [args.traversal] if args.traversal else ["bf16", "f32"],
+            grid={"traversal": [args.traversal] if args.traversal else
+                  (["fp8", "bf16", "f32"] if cid == 3 else ["bf16", "f32"]),
                   "router_threshold": [args.router] if args.router is not None else [0, 512, 2048],
                   "hash_cap": [args.hash_cap] if args.hash_cap else [4096, 8192]},
             reps=args.reps, log=log)
@@ -231,6 +237,9 @@ def main():
                                          "hash_cap")}
         fixed_best = fixed_sweep("fixed_batched", bkw)
 
+    if not args.plain_only and args.ef_max < k:
+        log(f"learned form skipped: --ef-max {args.ef_max} < k = {k}")
+    elif not args.plain_only:
         # ---- learned: traces of separate training queries, GPU training ------------------
         t0 = time.time()
         wt = synth.make_workload(cid, n=n, nq=args.ntrain, query_stream=5000, range_stream=6000)
@@ -278,6 +287,8 @@ def main():
     # ---- operating point and timed region -----------------------------------------
     if lkw is not None:
         mode, ef, kw, best = "learned_batched", args.ef_max, lkw, learned_best
+    elif fixed_best is not None and fixed_best["recall"] >= TARGET_RECALL:
+        mode, ef, kw, best = "fixed_batched", fixed_best["ef"], dict(bkw), fixed_best
     else:
         mode, ef, kw, best = "plain_f32", plain_best["ef"], dict(plain_kw), plain_best
     log(f"operating point: {mode} {best}")
@@ -292,6 +303,18 @@ def main():
     ms_per_step = wall * 1000.0 / args.steps
     qps = nq / (ms_per_step / 1000.0)
     rec_timed = recall(ids, dists)
+    # float32 distances returned against float64 ones over the returned points
+    samp = np.arange(0, nq, max(1, nq // 500))
+    ids_h, d_h = ids[samp].cpu().numpy(), dists[samp].cpu().numpy()
+    rel = []
+    for i, qi in enumerate(samp):
+        ok = ids_h[i] >= 0
+        diff = X[ids_h[i][ok]].astype(np.float64) - w["Q"][qi].astype(np.float64)
+        d64 = (diff * diff).sum(1)
+        rel.append(np.abs(d_h[i][ok].astype(np.float64) - d64) / np.maximum(d64, 1e-30))
+    rel = np.concatenate(rel) if rel else np.zeros(1)
+    dist_err = {"max_rel": float(rel.max()), "mean_rel": float(rel.mean()),
+                "queries": int(len(samp))}
 
     # ---- roofline of the dominant kernel (graph search over the wide queries) --------
     skw = {kk: v for kk, v in kw.items() if kk not in ("router_threshold", "use_graph")}
@@ -310,7 +333,7 @@ def main():
         ix.search_ex(Qw, lw, rw, k, ef, trace=tr, **skw)
     torch.cuda.synchronize()
     trace = esg.decode_trace(tr)
-    elem = 2 if skw.get("traversal") == "bf16" else 4
+    elem = {"bf16": 2.0, "fp8": 1.0 + 4.0 / d}.get(skw.get("traversal"), 4.0)
     alg_bytes = algorithmic_bytes(trace, d, info["degree"], k, m_part, elem,
                                   skw.get("rerank", False))
     iw = torch.empty((nw, k), dtype=torch.int64, device=dev)
@@ -348,11 +371,13 @@ def main():
                          f"ef={plain_best['ef']}, OpenMP over queries; {el:.1f}s"}
         log(f"cpu oracle {done / el:,.0f} q/s on {cores} cores over {done} queries")
 
-    wl = (f"deep-shaped N={n} d={d} unit-norm, {nq} queries, widths log-uniform 10..N, k={k}"
-          if cid == 2 else
-          f"sift-shaped N={n} d={d} uint8-valued, {nq} queries, 11 width buckets 2^-b*N, k={k}")
+    wl = {2: f"deep-shaped N={n} d={d} unit-norm, {nq} queries, widths log-uniform 10..N, k={k}",
+          1: f"sift-shaped N={n} d={d} uint8-valued, {nq} queries, 11 width buckets 2^-b*N, k={k}",
+          3: f"embedding-shaped N={n} d={d} unit-norm, {nq} queries, 13 width buckets 2^-b*N, "
+             f"k={k}"}[cid]
     out = {
-        "metric": "QPS at recall@10>=0.95, learned+batched vs plain search, 1 MI355X; HBM GB/s",
+        "metric": "QPS at recall@10>=0.95, learned+batched vs plain search, 1 MI355X; HBM GB/s"
+                  if k == 10 else f"QPS at recall@{k}>=0.95, 1 MI355X; HBM GB/s",
         "value": round(qps, 1),
         "unit": "queries/s",
         "n_gpus": 1,
@@ -362,9 +387,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16+f32" if kw.get("traversal") == "bf16" else "f32",
+        "dtype": {"bf16": "bf16+f32", "fp8": "fp8+f32"}.get(kw.get("traversal"), "f32"),
         "data": "synthetic",
-        "config": {"workload": wl, "variant": mode, "recall_at_10": round(rec_timed, 5),
+        "config": {"workload": wl, "variant": mode, f"recall_at_{k}": round(rec_timed, 5),
+                   "traversal": kw.get("traversal", "f32"), "distance_error_vs_f64": dist_err,
                    "ef": ef, "delta": best.get("delta"), "target": best.get("target"),
                    "router_threshold": kw.get("router_threshold", 0),
                    "hash_cap": kw.get("hash_cap", 0), "probe_hops": args.probe_hops,

@@ -59,14 +59,6 @@ __device__ __forceinline__ uint32_t* wave_table(WaveLds* L) {
 
 // ---- distances ------------------------------------------------------------
 
-// OCP E4M3 code to float32, exact.
-__device__ __forceinline__ float e4m3_to_f32(uint32_t c) {
-  uint32_t s = (c & 0x80u) << 24;
-  uint32_t e = (c >> 3) & 15u, m = c & 7u;
-  float v = (e == 0u) ? (float)m * 0.001953125f : __uint_as_float(((e + 120u) << 23) | (m << 20));
-  return __uint_as_float(__float_as_uint(v) | s);
-}
-
 template <int KIND>
 __device__ __forceinline__ uint4 load_chunk(const SearchArgs& A, uint32_t id, int ch) {
   const uint4* p;
@@ -97,10 +89,15 @@ __device__ __forceinline__ float chunk_acc(const uint4& raw, const float* qc, fl
       acc = sqacc(__uint_as_float(h), qc[e], acc);
     }
   } else {
+    // gfx950 converts two OCP E4M3 bytes to float32 per instruction (exact)
 #pragma unroll
-    for (int e = 0; e < 16; e++) {
-      uint32_t c = (w[e >> 2] >> (8 * (e & 3))) & 0xFFu;
-      acc = sqacc(scale * e4m3_to_f32(c), qc[e], acc);
+    for (int j = 0; j < 4; j++) {
+      const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[j], false);
+      const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[j], true);
+      acc = sqacc(scale * lo[0], qc[4 * j + 0], acc);
+      acc = sqacc(scale * lo[1], qc[4 * j + 1], acc);
+      acc = sqacc(scale * hi[0], qc[4 * j + 2], acc);
+      acc = sqacc(scale * hi[1], qc[4 * j + 3], acc);
     }
   }
   return acc;

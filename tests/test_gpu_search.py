@@ -55,6 +55,20 @@ def tiny32(tmp_path_factory):
     gix.free()
 
 
+@pytest.fixture(scope="module")
+def emb(tmp_path_factory):
+    """Embedding-shaped workload at reduced size (N=12,000 unit-norm vectors
+    in d=768, 40 queries, k=100 in the tests), degree 32, leaf bound 256."""
+    w = synth.make_workload(3, n=12000, nq=40)
+    path = str(tmp_path_factory.mktemp("emb") / "emb.esgi")
+    esg.build_index(w["X"], w["attr"].astype(np.float64), path, degree=32, leaf=256,
+                    ef_construction=100)
+    gix = esg.Index(path, 0)
+    oix = oracle.read_index(path)
+    yield w, gix, oix, path
+    gix.free()
+
+
 def gpu_search(gix, Q, l, r, k, ef, visited_cap=0, **kw):
     nq = len(Q)
     tr = esg.trace_tensor(nq, DEV)
@@ -216,6 +230,23 @@ def test_tiny_bf16_fp8_traversal(tiny):
 def test_degree32_parity(tiny32, k, ef, trav):
     """Degree-32 graphs: expansions of up to 32 neighbours."""
     w, gix, oix, path = tiny32
+    kind = {"f32": oracle.DIST_F32, "bf16": oracle.DIST_BF16, "fp8": oracle.DIST_FP8}[trav]
+    oi = oix
+    if trav != "f32":
+        gix.add_storage(trav)
+        oi = oracle.read_index(path)
+        oi = oi.with_bf16() if trav == "bf16" else oi.with_fp8()
+    Q, l, r = w["Q"], w["l"], w["r"]
+    out = gpu_search(gix, Q, l, r, k, ef, visited_cap=8192, traversal=trav, rerank=trav != "f32")
+    check_against_oracle(w, oi, out, Q, l, r, k, ef, kind=kind, rerank=int(trav != "f32"))
+
+
+@pytest.mark.parametrize("k,ef,trav", [(100, 128, "f32"), (100, 128, "bf16"), (100, 128, "fp8"),
+                                       (100, 256, "fp8"), (10, 64, "bf16")])
+def test_embedding_parity(emb, k, ef, trav):
+    """d = 768 (three, two and one 16-byte chunks per lane for float32,
+    bfloat16, fp8), k = 100, with the float32 rerank for narrow storage."""
+    w, gix, oix, path = emb
     kind = {"f32": oracle.DIST_F32, "bf16": oracle.DIST_BF16, "fp8": oracle.DIST_FP8}[trav]
     oi = oix
     if trav != "f32":
