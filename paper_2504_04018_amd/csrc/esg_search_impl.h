@@ -10,12 +10,14 @@
 //  - P (candidates) and Q (results) are sorted ascending lists of 64-bit
 //    keys (float distance bits above the position), held in registers as
 //    E words per lane; element i lives in word i/64 of lane i%64.
-//  - One expansion reads a 64-byte adjacency row (16 lanes x 4 B), tests
-//    and sets the visited bits in an LDS hash (global bitmap once the hash
-//    is 3/4 full), gathers the new neighbours' vectors with 16-byte loads
-//    (G lanes per vector), reduces each distance across its G lanes, sorts
-//    the <= 16 new keys with a bitonic network and merges them into P and
-//    (the in-range ones) into Q with a bitonic merge.
+//  - One expansion reads the adjacency row of the popped candidate (R <= 32
+//    lanes x 4 B, prefetched while the previous expansion merges), tests
+//    and sets the visited entries in an exact LDS hash (a global bitmap
+//    takes new keys once the hash is 3/4 full), gathers the new
+//    neighbours' vectors with 16-byte loads (G lanes per vector), reduces
+//    each distance across its G lanes, drops keys that lose to a full Q,
+//    sorts the rest (<= 32) with a bitonic network and merges them into P
+//    and (the in-range ones) into Q.
 //  - Merging a whole expansion at once gives the same P, Q and visited set
 //    as inserting the neighbours one by one (Alg. 1 cuts Q back to m only
 //    after the neighbour loop; P keeps its cand_cap best).

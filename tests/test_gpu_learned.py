@@ -176,3 +176,60 @@ def test_learned_stop_parity(tiny, delta, probe):
         assert np.array_equal(ids[i], oid), i
         assert np.array_equal(dists[i].view(np.uint32), od.view(np.uint32)), i
     assert switched > 50 and cut > 10
+
+
+def test_network_reduces_work():
+    """What the trained network gains over the method without it: on a
+    DEEP-shaped set (N=60,000, d=96) the learned beam width, trained on the
+    GPU from traces of separate training queries, reaches the recall of the
+    fixed-ef search with fewer expansions (hops, interpolated along both
+    recall curves). Work is counted in hops, so the result does not depend
+    on timing."""
+    from paper_2504_04018_amd import learned
+    import os
+    import tempfile
+    w = synth.make_workload(2, n=60000, nq=4000)
+    wt = synth.make_workload(2, n=60000, nq=30000, query_stream=5000, range_stream=6000)
+    path = os.path.join(tempfile.mkdtemp(), "deep60k.esgi")
+    esg.build_index(w["X"], w["attr"].astype(np.float64), path, degree=32, leaf=1024,
+                    ef_construction=100)
+    ix = esg.Index(path, 0)
+    ix.add_storage("bf16")                 # the exact scan's MFMA pass reads it
+    ix.reserve(30000, 65536)
+    k = 10
+    Q, l, r = _t(w["Q"]), _t(w["l"]), _t(w["r"])
+    Qt, lt, rt = _t(wt["Q"]), _t(wt["l"]), _t(wt["r"])
+    _, gt = learned.exact_answers(ix, Q, l, r, k)
+    _, gtt = learned.exact_answers(ix, Qt, lt, rt, k)
+    width = r - l + 1
+
+    def run(ef, **kw):
+        tr = esg.trace_tensor(len(Q), DEV)
+        ids, d = ix.search_ex(Q, l, r, k, ef, trace=tr, **kw)
+        rec = float(learned.per_query_recall(ids, d, gt, width, k).mean())
+        hops = int(esg.decode_trace(tr)["hops"].sum())
+        return rec, hops
+
+    fixed = [run(ef) for ef in (10, 11, 12, 13, 14, 16, 18, 20, 24, 28, 32)]
+    F, T = learned.traces(ix, Qt, lt, rt, k, [10, 12, 14, 16, 18, 20, 22, 24, 28, 32], 32, 4,
+                          {}, gtt)
+    params, hist = learned.train(F, T)
+    assert hist[-1] < hist[0]
+    lrn = [run(32, mlp=params, probe_hops=4, mlp_delta=dl) for dl in np.arange(-1.0, 1.51, 0.125)]
+
+    def hops_at(curve, rec):
+        """Hops needed for mean recall `rec`, interpolated along the curve."""
+        pts = sorted(curve, key=lambda t: t[1])
+        for (r0, h0), (r1, h1) in zip(pts, pts[1:]):
+            if r0 < rec <= r1:
+                return h0 + (h1 - h0) * (rec - r0) / (r1 - r0)
+        return min(h for rc, h in pts if rc >= rec) if any(rc >= rec for rc, _ in pts) else None
+
+    # the recall of the fixed search at ef 16 (this small set is easier than
+    # the 1M one, so the comparison sits higher on the recall curve)
+    target = fixed[5][0]
+    hf, hl = hops_at(fixed, target), hops_at(lrn, target)
+    print(f"[learned] recall {target:.4f}: fixed {hf:.0f} hops, learned {hl:.0f} hops "
+          f"({hl / hf:.3f}); fixed {fixed}; learned {lrn}", flush=True)
+    ix.free()
+    assert hl is not None and hl <= 0.95 * hf
