@@ -38,6 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 TARGET_RECALL = 0.95
 EF_GRID = [10, 12, 14, 16, 18, 20, 22, 24, 28, 32, 40, 48, 64, 96, 100, 112, 128, 192, 256, 384, 512, 768, 1024]
 DELTA_GRID = [-1.0, -0.75, -0.5, -0.375, -0.25, -0.125, 0.0, 0.25, 0.5]
@@ -75,6 +76,9 @@ def parse():
     ap.add_argument("--target", choices=["ef", "hops"], default=None,
                     help="learned target (default: both, the faster kept)")
     ap.add_argument("--delta", type=float, default=None, help="learned offset (default: swept)")
+    ap.add_argument("--scan-only", action="store_true",
+                    help="time only the exact MFMA range scan over the workload's queries "
+                         "(MFMA roofline), print one JSON line and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory 5 times and exit (calibrates the "
                          "HBM byte counters against a transfer of known size)")
@@ -182,6 +186,27 @@ def main():
     gt_ids, gt_d = learned.exact_answers(ix, Q, l, r, k)
     torch.cuda.synchronize()
     log(f"exact ground truth (MFMA scan) in {time.time() - t0:.1f}s")
+
+    if args.scan_only:
+        # exact scan: algorithmic flops 2*w*d per query (in-range points only)
+        wsum = float((width).sum().item())
+        alg_flops = 2.0 * wsum * d
+        t_ms, nfb = [], 0
+        for i in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, nfb = ix.scan(Q, l, r, k)
+            torch.cuda.synchronize()
+            if i >= args.warmup:
+                t_ms.append((time.perf_counter() - t0) * 1000.0)
+        ms = float(np.median(t_ms))
+        tf = alg_flops / (ms / 1000.0) / 1e12
+        print(json.dumps({"scan_only": True, "workload": args.workload, "n": n, "d": d, "nq": nq,
+                          "k": k, "ms_per_batch": round(ms, 3), "queries_per_s": round(nq / ms * 1e3),
+                          "alg_tflop_per_batch": round(alg_flops / 1e12, 3),
+                          "alg_tflops": round(tf, 1), "bf16_peak_tflops": MFMA_BF16_PEAK_TFLOPS,
+                          "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4), "n_fallback": int(nfb)}))
+        return
 
     def recall(ids, dists):
         return float(learned.per_query_recall(ids, dists, gt_d, width, k).mean().item())

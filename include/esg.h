@@ -182,7 +182,7 @@ typedef struct {
                             first use and replay it while the arguments stay
                             the same                                       */
   int32_t scan_rerank;   /* candidates recomputed in float32 by the scan
-                            (0 = default)                                  */
+                            (0 = default, as rerank_count below)          */
   const float* mlp;      /* device ESG_MLP_PARAMS floats, or NULL: the
                             learned beam width.  Each graph part runs
                             probe_hops expansions of Alg. 1 with m = ef
@@ -221,11 +221,15 @@ int32_t esg_index_reserve(esg_index* idx, int64_t max_queries, int64_t max_windo
 
 typedef struct {
   int32_t rerank_count;  /* candidates recomputed in float32 per query
-                            (0 = min(64E - 1, max(4k, 32)))               */
-  int32_t reserved;
+                            (0 = 64E - 1, the whole merged list: the most
+                            queries certified, the fewest exact rescans) */
+  int32_t flags;         /* bit 0 (ESG_SCAN_EXACT): skip the certificate and
+                            rescan every query exactly; other bits 0     */
   int32_t* certified;    /* device int32 [nq] out (1 = certified), or NULL */
   int64_t* n_fallback;   /* host int64 out: queries rescanned exactly, or NULL */
 } esg_scan_opts;
+
+#define ESG_SCAN_EXACT 1
 
 /* Exact range-filtered k-NN by brute force (Def. 2.1 / 2.2 with the float32
  * canonical distance, ties by position), for any range widths: candidates

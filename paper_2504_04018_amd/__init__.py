@@ -76,7 +76,7 @@ class SearchOpts(ctypes.Structure):
 
 
 class ScanOpts(ctypes.Structure):
-    _fields_ = [("rerank_count", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("rerank_count", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("certified", ctypes.c_void_p), ("n_fallback", ctypes.c_void_p)]
 
 
@@ -201,7 +201,7 @@ class Index:
         _check(lib().esg_index_reserve(self._h, max_queries, max_windows), "esg_index_reserve")
 
     def scan(self, queries, l, r, k: int, ids=None, dists=None, rerank_count: int = 0,
-             certified=None, stream=None):
+             certified=None, exact: bool = False, stream=None):
         """esg_scan_batch: exact range-filtered k-NN; returns (ids, dists, n_fallback)."""
         import torch
         nq = queries.shape[0]
@@ -214,8 +214,8 @@ class Index:
         if dists is None:
             dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
         nfb = ctypes.c_int64(0)
-        o = ScanOpts(rerank_count, 0, None if certified is None else certified.data_ptr(),
-                     ctypes.addressof(nfb))
+        o = ScanOpts(rerank_count, 1 if exact else 0,
+                     None if certified is None else certified.data_ptr(), ctypes.addressof(nfb))
         st = lib().esg_scan_batch(self._h, ctypes.byref(o), qp, lp, rp, nq, k,
                                   _dev(ids, torch.int64, (nq, k), "ids"),
                                   _dev(dists, torch.float32, (nq, k), "dists"),

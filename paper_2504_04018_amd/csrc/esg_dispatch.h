@@ -14,7 +14,8 @@ struct KernelTable {
   const void* mfma;                       // MFMA approximate distances
   const void* select[kNumScanWidths];     // per-window top list
   const void* rerank[kNumScanWidths];     // merge + float32 rerank + certificate
-  const void* fallback[kNumScanWidths];   // exact float32 scan
+  const void* fallback[kNumScanWidths];   // exact float32 scan of each window
+  const void* fb_merge[kNumScanWidths];   // merge of the windows' exact lists
 };
 
 }  // namespace esgk

@@ -649,9 +649,14 @@ int32_t launch_scan(esg_index* idx, esgk::ScanArgs& S, int64_t nw_bound, int64_t
   if (st == ESG_OK) st = launch_fn(idx->kt->select[wi], (nw_bound + 3) / 4, 0, &S, s);
   if (st == ESG_OK)
     st = launch_fn(idx->kt->rerank[wi], (nq_bound + 3) / 4, 4 * esgk::kStageBytes, &S, s);
+  // fallback: the window pass takes every resident wave slot (the windows of
+  // the few uncertified queries are spread over all of them)
   if (st == ESG_OK)
-    st = launch_fn(idx->kt->fallback[wi], std::min<int64_t>(1024, (nq_bound + 3) / 4),
+    st = launch_fn(idx->kt->fallback[wi], std::min<int64_t>(4 * (int64_t)idx->cu_count,
+                                                          (nw_bound + 3) / 4),
                    4 * esgk::kStageBytes, &S, s);
+  if (st == ESG_OK)
+    st = launch_fn(idx->kt->fb_merge[wi], std::min<int64_t>(1024, (nq_bound + 3) / 4), 0, &S, s);
   return st;
 }
 
@@ -670,8 +675,9 @@ int32_t esg_scan_batch(esg_index* idx, const esg_scan_opts* opts, const float* q
   std::memset(&o, 0, sizeof(o));
   if (opts) o = *opts;
   const int cap = 64 << scan_width_index(k);
-  const int mr = o.rerank_count > 0 ? o.rerank_count : std::min(cap - 1, std::max(4 * k, 32));
+  const int mr = o.rerank_count > 0 ? o.rerank_count : cap - 1;   // the whole list: fewest fallbacks
   if (mr < k || mr > cap - 1) return ESG_EINVAL;
+  if (o.flags & ~ESG_SCAN_EXACT) return ESG_EINVAL;
   if (hipSetDevice(idx->device) != hipSuccess) return ESG_EHIP;
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<int64_t> hl((size_t)nq), hr((size_t)nq);
@@ -724,6 +730,7 @@ int32_t esg_scan_batch(esg_index* idx, const esg_scan_opts* opts, const float* q
     if (!ok) return ESG_EHIP;
     zero_i32_kernel<<<1, 64, 0, s>>>(idx->counts, 4);
     esgk::ScanArgs S = scan_args(idx, queries, l, r, nq, k, mr, ids, dists, o.certified);
+    S.force_exact = (o.flags & ESG_SCAN_EXACT) ? 1 : 0;
     S.qlist = idx->qlist;
     S.nw = nw;
     S.nq_list = (int64_t)qlist.size();
@@ -831,7 +838,7 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
     if (nq > idx->res_queries || nq > idx->res_windows) return ESG_ERANGE;
     if (o.router_threshold > esgk::kWin) return ESG_EINVAL;
     const int cap = 64 << scan_width_index(k);
-    mr = o.scan_rerank > 0 ? o.scan_rerank : std::min(cap - 1, std::max(4 * k, 32));
+    mr = o.scan_rerank > 0 ? o.scan_rerank : cap - 1;
     if (mr < k || mr > cap - 1) return ESG_EINVAL;
   }
 

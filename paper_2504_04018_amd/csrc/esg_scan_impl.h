@@ -20,7 +20,8 @@
 //     q, float32 accumulation and norms) and g a float32 relative error bound:
 //     then no point outside the candidates can enter the top k.
 //  4. fallback: queries that are not certified are rescanned exactly
-//     (float32 canonical distances over the whole range).
+//     (float32 canonical distances): each window's exact top k, one wave
+//     per window, then one merge per query.
 #pragma once
 
 #include "esg_search_kernel.h"
@@ -61,6 +62,7 @@ struct ScanArgs {
   // outputs
   int64_t* ids;            // [nq][k]
   float* dists;            // [nq][k]
+  int32_t force_exact;     // 1: no certificate, every query is rescanned exactly
   int32_t* fb_list;        // [nq] queries that need the exact fallback
   int32_t* fb_count;       // [1]
   int32_t* certified;      // [nq] 1 when certified (optional, may be null)
@@ -305,6 +307,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(ScanArgs S) {
   } else if (next != kKeyInf && kth == kKeyInf) {
     certified = false;  // fewer than k reranked but more points exist
   }
+  if (S.force_exact) certified = false;
   if (S.certified && lane == 0) S.certified[qi] = certified ? 1 : 0;
   if (!certified) {
     if (lane == 0) {
@@ -327,28 +330,62 @@ __global__ __launch_bounds__(256) void rerank_kernel(ScanArgs S) {
 }
 
 // ---- 4. exact fallback ------------------------------------------------------------
+// 4a. Every window of an uncertified query gets its exact top k (float32
+// canonical distances, ties by position), written over the window's
+// candidate list.  All waves walk the (short) fallback list; the windows of
+// one query are spread over the waves, so a wide range is rescanned by
+// hundreds of waves at once.
 template <int G32, int CPL32, int E>
-__global__ __launch_bounds__(256) void fallback_kernel(ScanArgs S) {
+__global__ __launch_bounds__(256) void fallback_window_kernel(ScanArgs S) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int lane = lane_id();
   const int wave = threadIdx.x >> 6;
   WaveLds* Ls = reinterpret_cast<WaveLds*>(smem + (size_t)wave * kStageBytes);
   const int64_t nfb = *S.fb_count;
-  const int k = S.k;
+  const int64_t gw = (int64_t)blockIdx.x * 4 + wave, nwaves = (int64_t)gridDim.x * 4;
   SearchArgs A;
   A.vec = S.vec;
   A.d = S.d;
   A.dp = S.dp;
+  for (int64_t t = 0; t < nfb; t++) {
+    const int32_t qi = S.fb_list[t];
+    const int64_t w0 = S.q_win0[qi], nwq = S.q_nwin[qi];
+    if (gw >= nwq) continue;
+    float qr32[CPL32][4];
+    load_query<kF32, G32, CPL32>(S.queries + (int64_t)qi * S.d, S.d, lane, qr32);
+    for (int64_t j = gw; j < nwq; j += nwaves) {
+      Part pt;
+      pt.x = (uint32_t)S.win_s[w0 + j];
+      pt.y = (uint32_t)S.win_e[w0 + j];
+      uint64_t R[E];
+      scan_leaf<G32, CPL32, E>(A, Ls, pt, S.k, qr32, R, lane);
+      uint64_t* out = S.cand + (w0 + j) * S.cand_stride;
+#pragma unroll
+      for (int e = 0; e < E; e++) out[e * kWave + lane] = R[e];
+    }
+  }
+}
+
+// 4b. One wave per uncertified query merges its windows' exact lists and
+// writes the top k (the top k of a union is inside the union of top k's).
+template <int E>
+__global__ __launch_bounds__(256) void fallback_merge_kernel(ScanArgs S) {
+  const int lane = lane_id();
+  const int wave = threadIdx.x >> 6;
+  const int64_t nfb = *S.fb_count;
+  const int k = S.k;
   for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < nfb; t += (int64_t)gridDim.x * 4) {
     const int32_t qi = S.fb_list[t];
-    const float* q = S.queries + (int64_t)qi * S.d;
-    float qr32[CPL32][4];
-    load_query<kF32, G32, CPL32>(q, S.d, lane, qr32);
-    Part pt;
-    pt.x = (uint32_t)S.l[qi];
-    pt.y = (uint32_t)S.r[qi];
+    const int64_t w0 = S.q_win0[qi], nwq = S.q_nwin[qi];
     uint64_t R[E];
-    scan_leaf<G32, CPL32, E>(A, Ls, pt, k, qr32, R, lane);
+    list_clear(R);
+    for (int64_t j = 0; j < nwq; j++) {
+      const uint64_t* c = S.cand + (w0 + j) * S.cand_stride;
+      uint64_t B[E];
+#pragma unroll
+      for (int e = 0; e < E; e++) B[e] = c[e * kWave + lane];
+      list_merge(R, B, k, lane);
+    }
     int64_t* ids = S.ids + (int64_t)qi * k;
     float* dists = S.dists + (int64_t)qi * k;
 #pragma unroll

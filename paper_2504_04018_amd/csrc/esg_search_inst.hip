@@ -50,7 +50,8 @@ void fill_scan(KernelTable* t, int slot) {
   using S32 = Shape<kF32>;
   t->select[slot] = reinterpret_cast<const void*>(&select_kernel<E>);
   t->rerank[slot] = reinterpret_cast<const void*>(&rerank_kernel<S32::G, S32::CPL, E>);
-  t->fallback[slot] = reinterpret_cast<const void*>(&fallback_kernel<S32::G, S32::CPL, E>);
+  t->fallback[slot] = reinterpret_cast<const void*>(&fallback_window_kernel<S32::G, S32::CPL, E>);
+  t->fb_merge[slot] = reinterpret_cast<const void*>(&fallback_merge_kernel<E>);
 }
 
 constexpr int kDp = (ESG_DIM + 15) / 16 * 16;

@@ -92,6 +92,22 @@ def test_scan_exact(idx, k):
     assert c.mean() > 0.5
 
 
+@pytest.mark.parametrize("k", [1, 10, 100])
+def test_scan_forced_exact(idx, k):
+    """Every query through the exact path (each window's exact top k, then a
+    merge per query): equal to the float32 scan, all counted as rescans."""
+    w, gix, oix = idx
+    l, r = mixed_ranges(oix.n, 200, 100 + k)
+    Q = w["Q"][np.arange(200) % len(w["Q"])]
+    print(f"[gpu] exact scan k={k}", flush=True)
+    ids, dists, nfb = gix.scan(_t(Q), _t(l), _t(r), k, exact=True)
+    torch.cuda.synchronize()
+    oid, od = oracle_scan(oix, Q, l, r, k)
+    assert nfb == 200
+    assert np.array_equal(ids.cpu().numpy(), oid)
+    assert np.array_equal(dists.cpu().numpy().view(np.uint32), od.view(np.uint32))
+
+
 def test_scan_invalid_and_tiny_ranges(idx):
     w, gix, oix = idx
     l = np.array([0, 5, 9999, 3, -1, 10, 0], np.int64)
