@@ -138,6 +138,10 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
   const uint32_t* rows = A.adj + (size_t)pt.depth * (size_t)A.n * (size_t)A.R;
   const uint32_t ep = A.ep[pt.heap];
 
+  // The entry's adjacency row is requested together with its vector, so the
+  // two loads overlap.
+  uint32_t vrow = lane < A.R ? rows[(size_t)ep * A.R + lane] : kNoNode;
+
   // P <- ep ; Q <- ep when ep is in range (POST)
   visit(A, V, ep, lane == 0, lane);
   float dep = batch_dist<KIND, G, CPL>(A, ep, 1, qr, Ls, lane);
@@ -155,8 +159,7 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
   // The row of the next candidate is fetched as soon as that candidate is
   // known (right after the new batch is sorted), so the load overlaps the
   // merges of the current expansion.
-  uint64_t u = readlane64(P[0], 0);
-  uint32_t vrow = lane < A.R ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
+  uint64_t u = kep;                                          // P[0]; its row is vrow
   auto expand = [&](bool probe_phase) {
     for (;;) {
       if (u == kKeyInf) break;                                   // P is empty

@@ -278,3 +278,35 @@ def test_argument_errors(tiny):
     with pytest.raises(esg.EsgError) as e:
         gix.search_ex(Q, l, r, 10, 64, hash_cap=32768)
     assert e.value.status == esg.ESG_EINVAL
+
+
+@pytest.mark.parametrize("nq", [0, 1, 3, 65])
+def test_empty_and_ragged_batches(tiny, nq):
+    """Batches of 0, 1, 3 and 65 queries (not multiples of the 4 waves of a
+    workgroup): plain search, bfloat16 search replayed from a hipGraph, and
+    the exact scan at its largest k (128), each against the oracle."""
+    from test_gpu_scan import oracle_scan
+    w, gix, oix, path = tiny
+    gix.add_storage("bf16")
+    gix.reserve(256, 4096)
+    o16 = oracle.read_index(path).with_bf16()
+    Q, l, r = w["Q"][:nq], w["l"][:nq], w["r"][:nq]
+    for kw, oi, kind, rer in (({}, oix, oracle.DIST_F32, 0),
+                              ({"use_graph": True, "traversal": "bf16", "rerank": True}, o16,
+                               oracle.DIST_BF16, 1)):
+        print(f"[gpu] ragged nq={nq} {kw}", flush=True)
+        ids, dists = gix.search_ex(_t(Q), _t(l), _t(r), 10, 64, **kw)
+        torch.cuda.synchronize()
+        assert ids.shape == (nq, 10)
+        if nq:
+            oid, od, st = oracle.query_batch(oi, Q, l, r, 10, 64, 64, -1, kind, rer)
+            assert np.all(st == 0)
+            assert np.array_equal(ids.cpu().numpy(), oid)
+            assert np.array_equal(dists.cpu().numpy().view(np.uint32), od.view(np.uint32))
+    ids, dists, nfb = gix.scan(_t(Q), _t(l), _t(r), 128)
+    torch.cuda.synchronize()
+    assert ids.shape == (nq, 128)
+    if nq:
+        oid, od = oracle_scan(oix, Q, l, r, 128)
+        assert np.array_equal(ids.cpu().numpy(), oid)
+        assert np.array_equal(dists.cpu().numpy().view(np.uint32), od.view(np.uint32))
