@@ -842,8 +842,9 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
     if (mr < k || mr > cap - 1) return ESG_EINVAL;
   }
 
-  const bool learn = (o.mlp || o.feat_out) && o.probe_hops > 0;   // kernel with the switch
-  const void* fn = idx->kt->fn[o.traversal][width_index(std::max(ef, cand_cap))][learn ? 1 : 0];
+  // kernel: plain, or with the learned switch after a one-hop or a longer probe
+  const int learn = ((o.mlp || o.feat_out) && o.probe_hops > 0) ? (o.probe_hops == 1 ? 1 : 2) : 0;
+  const void* fn = idx->kt->fn[o.traversal][width_index(std::max(ef, cand_cap))][learn];
   if (!fn) return ESG_EUNSUPPORTED;
 
   esgk::SearchArgs a;

@@ -22,7 +22,7 @@ struct Shape {
   static constexpr int CPL = (C + G - 1) / G;
 };
 
-template <int KIND, int E, bool LEARN>
+template <int KIND, int E, int LEARN>
 const void* kernel_ptr() {
   using S = Shape<KIND>;
   using S32 = Shape<kF32>;
@@ -30,7 +30,7 @@ const void* kernel_ptr() {
       &search_kernel<KIND, S::G, S::CPL, S32::G, S32::CPL, E, LEARN>);
 }
 
-template <int KIND, bool LEARN>
+template <int KIND, int LEARN>
 void fill_one(KernelTable* t) {
   t->fn[KIND][0][LEARN] = kernel_ptr<KIND, 1, LEARN>();
   t->fn[KIND][1][LEARN] = kernel_ptr<KIND, 2, LEARN>();
@@ -41,8 +41,9 @@ void fill_one(KernelTable* t) {
 
 template <int KIND>
 void fill(KernelTable* t) {
-  fill_one<KIND, false>(t);
-  fill_one<KIND, true>(t);
+  fill_one<KIND, 0>(t);   // plain
+  fill_one<KIND, 1>(t);   // learned switch after a one-hop probe
+  fill_one<KIND, 2>(t);   // learned switch after a longer probe
 }
 
 template <int E>

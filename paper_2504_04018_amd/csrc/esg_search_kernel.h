@@ -122,10 +122,10 @@ __device__ __forceinline__ float probe_feature(int lane, float wp, float L, int6
 #ifndef ESG_LEARN_RF
 #define ESG_LEARN_RF 4
 #endif
-template <int KIND, bool LEARN>
-constexpr int kLearnRF = LEARN ? (KIND == kF32 ? 8 : ESG_LEARN_RF) : 8;
+template <int KIND, int LEARN>
+constexpr int kLearnRF = LEARN != 0 ? (KIND == kF32 ? 8 : ESG_LEARN_RF) : 8;
 
-template <int KIND, int G, int CPL, int E, bool LEARN>
+template <int KIND, int G, int CPL, int E, int LEARN>
 __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* Ls, Visited& V,
                                                   const Part& pt, int m, int cap_p,
                                                   const float (&qr)[CPL][Traits<KIND>::W],
@@ -160,13 +160,16 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
   // known (right after the new batch is sorted), so the load overlaps the
   // merges of the current expansion.
   uint64_t u = kep;                                          // P[0]; its row is vrow
-  auto expand = [&](bool probe_phase) {
-    for (;;) {
-      if (u == kKeyInf) break;                                   // P is empty
-      if (probe_phase && hops == A.probe_hops) break;           // probe over: switch first
+  // One expansion of Alg. 1 (pop the nearest candidate, visit its
+  // neighbours, score the new ones, merge them into P and Q); false when the
+  // search (or, in the probe phase, the probe) ends instead.
+  auto hop = [&](bool probe_phase) -> bool {
+    {
+      if (u == kKeyInf) return false;                            // P is empty
+      if (probe_phase && hops == A.probe_hops) return false;    // probe over: switch first
       const uint64_t worst = list_at(Q, m - 1);
-      if (worst != kKeyInf && worst < u) break;                  // farther than a full Q
-      if (hop_limit >= 0 && hops >= hop_limit) break;
+      if (worst != kKeyInf && worst < u) return false;           // farther than a full Q
+      if (hop_limit >= 0 && hops >= hop_limit) return false;
       list_pop(P, lane);
       hops++;
 
@@ -177,14 +180,14 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
       if (n_new == 0) {
         u = readlane64(P[0], 0);
         vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
-        continue;
+        return true;
       }
       if (is_new) Ls->ids[rank_below(nm)] = v;
       wave_lds_sync();
       const uint32_t nid = lane < n_new ? Ls->ids[lane] : kNoNode;
       if (dump && lane < n_new && nvis + lane < A.visited_cap) dump[nvis + lane] = nid;
       nvis += n_new;
-      n_inr += __popcll(ballot(lane < n_new && nid >= pt.x && nid <= pt.y));
+      if (probe_phase) n_inr += __popcll(ballot(lane < n_new && nid >= pt.x && nid <= pt.y));
 
       const float bd = batch_dist<KIND, G, CPL, kLearnRF<KIND, LEARN>>(A, nid, n_new, qr, Ls, lane);
       uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
@@ -197,7 +200,7 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
       if (sm == 0) {
         u = p0;
         vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
-        continue;
+        return true;
       }
       if (__popcll(sm) <= kInsertMax) {
         // few survivors: insert them one by one
@@ -211,7 +214,7 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
           const uint32_t pj = key_pos(kj);
           if (pj >= pt.x && pj <= pt.y) list_insert(Q, kj, m, lane);
         }
-        continue;
+        return true;
       }
       key = sort32(key, lane);
       const uint64_t kmin0 = readlane64(key, 0);
@@ -229,12 +232,20 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
         list_merge32(Q, Ls->stage[lane], m, lane);
       }
     }
+    return true;
   };
-  // The learned kernel runs the probe and the rest of the search as two
-  // copies of the loop, with the switch between them (no switch code
-  // inside a loop keeps register pressure at the plain kernel's level).
-  expand(LEARN);
-if (LEARN && u != kKeyInf && hops == A.probe_hops) {
+  // Plain kernel: hops until the search ends.  Learned kernel with a one-hop
+  // probe: the first hop and the switch come before the loop, which is then
+  // the plain kernel's loop.  Learned kernel with a longer probe: a probe
+  // loop, the switch, then the main loop.
+  bool go = true;
+  if constexpr (LEARN == 1) {
+    go = A.probe_hops == 1 && hop(true);
+  } else if constexpr (LEARN == 2) {
+    while (hop(true)) {
+    }
+  }
+  if (LEARN != 0 && go && u != kKeyInf && hops == A.probe_hops) {
     // probe over: features -> predicted beam width or stopping step
     int qsize = 0, psize = 0;
 #pragma unroll
@@ -281,8 +292,10 @@ if (LEARN && u != kKeyInf && hops == A.probe_hops) {
         pc.feat[kFeat + 1] = (float)efp;
       }
     }
-    expand(false);
   }
+  if (go)
+    while (hop(false)) {
+    }
   return {hops, nvis};
 }
 
@@ -337,7 +350,7 @@ __device__ __forceinline__ void rerank_f32(const SearchArgs& A, WaveLds* Ls, int
   for (int e = 0; e < E; e++) Q[e] = R[e];
 }
 
-template <int KIND, int G, int CPL, int G32, int CPL32, int E, bool LEARN>
+template <int KIND, int G, int CPL, int G32, int CPL32, int E, int LEARN>
 __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, Visited& V,
                                               int64_t qi, int lane) {
   const int k = A.k;
@@ -428,12 +441,12 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
 // bfloat16 kernels with 64 keys are held to 4 waves per SIMD (measured: the
 // few spills this costs are cheaper than a lost wave on these latency-bound
 // kernels); the others keep the compiler's choice.
-template <int KIND, int E, bool LEARN>
+template <int KIND, int E, int LEARN>
 constexpr int min_waves() {
   return ((KIND == kF32 && E <= 2) || (KIND == kBF16 && E == 1)) ? 4 : 1;
 }
 
-template <int KIND, int G, int CPL, int G32, int CPL32, int E, bool LEARN>
+template <int KIND, int G, int CPL, int G32, int CPL32, int E, int LEARN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<KIND, E, LEARN>(), 8)))
 void search_kernel(SearchArgs A) {
   extern __shared__ __align__(16) uint8_t smem[];

@@ -88,7 +88,7 @@ def tiny(tmp_path_factory):
     gix.free()
 
 
-@pytest.mark.parametrize("delta,probe", [(0.0, 8), (1.5, 4), (-3.0, 16)])
+@pytest.mark.parametrize("delta,probe", [(0.0, 8), (1.5, 4), (-3.0, 16), (0.5, 1)])
 def test_learned_search_parity(tiny, delta, probe):
     """Features after the probe equal the oracle's float64 features (1e-4);
     with the GPU's beam widths the oracle reproduces ids and distances."""
@@ -136,7 +136,7 @@ def test_learned_search_parity(tiny, delta, probe):
     assert switched > 50
 
 
-@pytest.mark.parametrize("delta,probe", [(0.0, 4), (2.0, 8)])
+@pytest.mark.parametrize("delta,probe", [(0.0, 4), (2.0, 8), (1.0, 1)])
 def test_learned_stop_parity(tiny, delta, probe):
     """Stopping-step target: every switched part takes at most the granted
     expansions after the probe, and the oracle, given those grants,
