@@ -105,12 +105,6 @@ __device__ __forceinline__ float chunk_acc(const uint4& raw, const float* qc, fl
   return acc;
 }
 
-template <int G>
-__device__ __forceinline__ float group_sum(float acc, int lane) {
-#pragma unroll
-  for (int s = 1; s < G; s <<= 1) acc = acc + xor_f(acc, s, lane);
-  return acc;
-}
 
 template <int KIND, int G, int CPL>
 __device__ __forceinline__ void load_query(const float* q, int d, int lane,
@@ -128,7 +122,7 @@ __device__ __forceinline__ void load_query(const float* q, int d, int lane,
 
 // Distances of up to 32 vectors whose positions sit in lanes 0..n_new-1 of
 // `nid`.  Returns lane j's distance (j < n_new).
-template <int KIND, int G, int CPL, int RFMAX = 8>
+template <int KIND, int G, int CPL, int RFMAX = 8, int TGMAX = (KIND == kF32 ? 8 : 1)>
 __device__ __forceinline__ float batch_dist(const SearchArgs& A, uint32_t nid, int n_new,
                                             const float (&qr)[CPL][Traits<KIND>::W], WaveLds* L,
                                             int lane) {
@@ -157,15 +151,49 @@ __device__ __forceinline__ float batch_dist(const SearchArgs& A, uint32_t nid, i
       if constexpr (KIND == kFP8) sc[rr] = ok ? A.scale8[id] : 0.0f;
       else sc[rr] = 1.0f;
     }
+    // Reduce TG rounds at a time across the G lanes of a vector: at the step
+    // with stride s < TG, the pair (t, t^s) adds its partial sums, lane t
+    // keeping one half of the rounds and t^s the other, so TG-1 exchanges
+    // replace TG*log2(TG) (a reduce-scatter); the remaining strides are a
+    // plain butterfly.  Every sum is still formed by the adjacent-pair tree
+    // (stride 1 first), so the result is bit-identical to reducing each
+    // round alone.  Lane t ends with round g0 + r(t), r(t) = sum_j
+    // bit_j(t) * TG/2^(j+1).
+    constexpr int TG = RF < TGMAX ? RF : TGMAX;
 #pragma unroll
-    for (int rr = 0; rr < RF; rr++) {
-      if ((r0 + rr) * VPG >= n_new) break;     // only occupied rounds are reduced
-      float acc = 0.0f;
+    for (int g0 = 0; g0 < RF; g0 += TG) {
+      if ((r0 + g0) * VPG >= n_new) break;    // only occupied groups are reduced
+      float acc[TG];
 #pragma unroll
-      for (int c = 0; c < CPL; c++) acc = chunk_acc<KIND>(raw[rr][c], qr[c], sc[rr], acc);
-      acc = group_sum<G>(acc, lane);
-      const int slot = (r0 + rr) * VPG + grp;
-      if (t == 0 && grp < VPG && slot < n_new) L->fstage[slot] = acc;
+      for (int rr = 0; rr < TG; rr++) {
+        acc[rr] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < CPL; c++)
+          acc[rr] = chunk_acc<KIND>(raw[g0 + rr][c], qr[c], sc[g0 + rr], acc[rr]);
+      }
+      int nv = TG;
+#pragma unroll
+      for (int s = 1; s < TG; s <<= 1) {
+        const bool upper = (lane & s) != 0;
+        nv >>= 1;
+#pragma unroll
+        for (int i = 0; i < TG / 2; i++) {
+          if (i < nv) {
+            const float lo = acc[i], hi = acc[i + nv];
+            const float keep = upper ? hi : lo, give = upper ? lo : hi;
+            acc[i] = keep + xor_f(give, s, lane);
+          }
+        }
+      }
+#pragma unroll
+      for (int s = TG; s < G; s <<= 1) acc[0] = acc[0] + xor_f(acc[0], s, lane);
+      if (t < TG) {
+        int r = 0;
+#pragma unroll
+        for (int s = 1, h = TG >> 1; s < TG; s <<= 1, h >>= 1) r += (t & s) ? h : 0;
+        const int slot = (r0 + g0 + r) * VPG + grp;
+        if (grp < VPG && slot < n_new) L->fstage[slot] = acc[0];
+      }
     }
   }
   wave_lds_sync();

@@ -124,6 +124,12 @@ __device__ __forceinline__ float probe_feature(int lane, float wp, float L, int6
 #endif
 template <int KIND, int LEARN>
 constexpr int kLearnRF = LEARN != 0 ? (KIND == kF32 ? 8 : ESG_LEARN_RF) : 8;
+// Rounds reduced together (reduce-scatter) in the distance pass: all of them
+// for float32; for narrow storage only in the learned kernels (measured:
+// the plain narrow kernels run faster with one round at a time, which needs
+// fewer registers).
+template <int KIND, int LEARN>
+constexpr int kReduceGroup = (KIND == kF32 || LEARN != 0) ? 8 : 1;
 
 template <int KIND, int G, int CPL, int E, int LEARN>
 __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* Ls, Visited& V,
@@ -189,7 +195,8 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
       nvis += n_new;
       if (probe_phase) n_inr += __popcll(ballot(lane < n_new && nid >= pt.x && nid <= pt.y));
 
-      const float bd = batch_dist<KIND, G, CPL, kLearnRF<KIND, LEARN>>(A, nid, n_new, qr, Ls, lane);
+      constexpr int kRF = kLearnRF<KIND, LEARN>, kTG = kReduceGroup<KIND, LEARN>;
+      const float bd = batch_dist<KIND, G, CPL, kRF, kTG>(A, nid, n_new, qr, Ls, lane);
       uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
       // A key that loses to a full Q can neither enter Q nor ever be expanded
       // (the bound only tightens), so dropping it leaves P's useful part, Q
