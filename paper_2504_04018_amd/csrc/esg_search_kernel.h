@@ -118,16 +118,12 @@ __device__ __forceinline__ float probe_feature(int lane, float wp, float L, int6
 
 // Gather rounds in flight per lane: the learned kernels with narrow storage
 // keep 4 instead of 8 to leave registers for the predictor (measured: fewer
-// spills beat more loads in flight there; the float32 one keeps 8).
-#ifndef ESG_LEARN_RF
-#define ESG_LEARN_RF 4
-#endif
+// spills beat more loads in flight there; the float32 ones keep 8).
 template <int KIND, int LEARN>
-constexpr int kLearnRF = LEARN != 0 ? (KIND == kF32 ? 8 : ESG_LEARN_RF) : 8;
+constexpr int kLearnRF = (LEARN != 0 && KIND != kF32) ? 4 : 8;
 // Rounds reduced together (reduce-scatter) in the distance pass: all of them
-// for float32; for narrow storage only in the learned kernels (measured:
-// the plain narrow kernels run faster with one round at a time, which needs
-// fewer registers).
+// for float32 and in the learned kernels; the plain narrow-storage kernels
+// reduce one round at a time (measured faster there: fewer registers).
 template <int KIND, int LEARN>
 constexpr int kReduceGroup = (KIND == kF32 || LEARN != 0) ? 8 : 1;
 
