@@ -26,6 +26,12 @@ MUTATIONS = {
         "list_insert(&Q, e);"),
     # Q cut to m-1
     "q_off_by_one": ("if (Q.len > m) Q.len = m;", "if (Q.len > m - 1) Q.len = m - 1;"),
+    # k-th feature taken one place too far down Q
+    "feature_kth_index": ("double qk = kk > 0 ? (double)Q->a[kk - 1].dist : d_ep;",
+                          "double qk = kk > 0 ? (double)Q->a[kk < Q->len ? kk : kk - 1].dist : d_ep;"),
+    # in-range share counted against |V| + 1
+    "feature_inrange_share": ("f[7] = (double)n_inr / (double)nv;",
+                              "f[7] = (double)n_inr / (double)(nv + 1);"),
     # split point rounded up
     "mid_rounded_up": ("int64_t mid = (a + b) / 2; /* a,b >= 0, so this is floor */",
                        "int64_t mid = (a + b + 1) / 2;"),

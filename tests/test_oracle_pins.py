@@ -280,6 +280,31 @@ def test_pre_post_worked_example():
     assert vis.tolist() == [pos["v0"], pos["v4"], pos["v1"], pos["v5"]]
 
 
+def test_learned_features_worked_example():
+    """The 12 probe features on the PRE/POST example, traced by hand: from
+    q = (0,0) the squared distances are v3 1, v2 9, v5 12.25, v4 20.25,
+    v0 32, v1 72.  After one expansion of the entry v0 (m = cap = 4):
+    P = {v2 9, v4 20.25, v1 72}, Q = {v4 20.25, v0 32, v1 72} (v2 is out of
+    range), V = {v0, v2, v4, v1} of which 3 are in range, and the next
+    candidate is v2 (9).  With k = 2, a query width of 5 and one part."""
+    ix, pos = _pre_post_index()
+    part = dict(depth=0, heap=1, a=0, b=5, x=1, y=5)
+    d, p, vis, hops, st, f = oracle.search_part_learned(
+        ix, part, np.zeros(2, np.float32), ef_max=4, switch_hop=1, ef2=0, k=2, w_query=5,
+        n_parts=1)
+    assert st == 0 and f is not None
+    want = [np.log2(5), np.log2(6), 5 / 6,        # filter width, node size, ratio
+            np.log2(5), 0.0,                       # query width, parts - 1
+            3 / 4, min(3 / 2, 4),                  # P fill of its cap, Q fill over k
+            3 / 4,                                 # in-range share of V
+            20.25 / 32, 32 / 32, 9 / 32,           # best and k-th in Q, best in P (ratios)
+            np.log2(1 + 4)]                        # log2(1 + |V|)
+    assert np.allclose(f, want, rtol=0, atol=1e-12), (f, want)
+    # the search itself is unchanged by a features-only switch
+    d0, p0, _, h0, _ = oracle.search_part(ix, part, np.zeros(2, np.float32), m=4, cap_p=4)
+    assert p.tolist() == p0.tolist() and hops == h0
+
+
 def test_post_short_q_keeps_searching():
     """Alg. 1 stop test read with a full-Q guard: under POST, Q holds only
     in-range points, so it may be short of m while an out-of-range
