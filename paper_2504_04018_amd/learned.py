@@ -37,14 +37,15 @@ def per_query_recall(ids, dists, gt_dists, width, k):
     return torch.minimum(hit.sum(1), kk).float() / kk.float()
 
 
-def traces(ix, Q, l, r, k, ef_grid, ef_max, probe_hops, search_kw, gt_dists, target="ef"):
+def traces(ix, Q, l, r, k, ef_grid, ef_max, probe_hops, search_kw, gt_dists, target="ef",
+           label_recall=1.0):
     """Features [n_samples, 12] and labels [n_samples].
 
     target "ef": the label is log2 of the smallest beam of ef_grid that
     reaches recall 1.  target "hops": the beam stays ef_max and ef_grid
     lists expansion grants G after the probe; the label is log2 of the
     smallest G (a per-part hop budget of probe_hops + G) that reaches
-    recall 1.  Either way log2(2 * max) when none does."""
+    recall 1 (or label_recall).  Either way log2(2 * max) when none does."""
     import torch
     nq = Q.shape[0]
     feat = torch.full((nq, 2, 16), float("nan"), device=Q.device)
@@ -58,7 +59,7 @@ def traces(ix, Q, l, r, k, ef_grid, ef_max, probe_hops, search_kw, gt_dists, tar
             ids, dists = ix.search_ex(Q, l, r, k, g, **search_kw)
         else:
             ids, dists = ix.search_ex(Q, l, r, k, ef_max, hop_budget=probe_hops + g, **search_kw)
-        ok = per_query_recall(ids, dists, gt_dists, width, k) >= 1.0
+        ok = per_query_recall(ids, dists, gt_dists, width, k) >= label_recall
         newly = ok & ~done
         need[newly] = math.log2(g)
         done |= ok
