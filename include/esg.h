@@ -195,7 +195,8 @@ typedef struct {
                             into the index's own inference layout on the
                             call's stream first (read-only here)          */
   int32_t probe_hops;    /* > 0 with mlp (or with feat_out alone: features
-                            only, no change of beam)                       */
+                            only, no change of beam).  1 selects a kernel
+                            whose switch comes before its search loop     */
   float mlp_delta;       /* calibration offset added to y                   */
   int32_t mlp_target;    /* 0: y sets the beam width as above; 1: y sets the
                             stopping step instead -- the part may take at
