@@ -168,3 +168,33 @@ def test_graph_replay(idx, thr):
         # unrelated eager work between replays
         gix.search_ex(Q[:50], lt[:50], rt[:50], 5, 32)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("probe", [1, 4])
+def test_router_with_learned_beam(idx, probe):
+    """Router + learned beam width + hipGraph replay: narrow queries equal the
+    float32 scan; wide ones equal the same learned search run without the
+    router on just those queries (the router only splits the batch)."""
+    w, gix, oix = idx
+    l, r = mixed_ranges(oix.n, 400, 300 + probe)
+    Q = w["Q"][np.arange(400) % len(w["Q"])]
+    rng = np.random.default_rng(5)
+    p = np.concatenate([rng.standard_normal(5057) * 0.15, rng.standard_normal(12),
+                        np.abs(rng.standard_normal(12)) + 0.5]).astype(np.float32)
+    p[5056] = 4.5
+    mlp = _t(p)
+    k, ef, thr = 10, 64, 1024
+    print(f"[gpu] router + learned probe={probe}", flush=True)
+    ids, dists = gix.search_ex(_t(Q), _t(l), _t(r), k, ef, router_threshold=thr, mlp=mlp,
+                               probe_hops=probe, use_graph=True)
+    torch.cuda.synchronize()
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    narrow = (r - l + 1) < thr
+    sid, sd = oracle_scan(oix, Q[narrow], l[narrow], r[narrow], k)
+    assert np.array_equal(ids[narrow], sid)
+    assert np.array_equal(dists[narrow].view(np.uint32), sd.view(np.uint32))
+    wi, wd = gix.search_ex(_t(Q[~narrow]), _t(l[~narrow]), _t(r[~narrow]), k, ef, mlp=mlp,
+                           probe_hops=probe)
+    torch.cuda.synchronize()
+    assert np.array_equal(ids[~narrow], wi.cpu().numpy())
+    assert np.array_equal(dists[~narrow].view(np.uint32), wd.cpu().numpy().view(np.uint32))
