@@ -1,0 +1,97 @@
+"""GPU parity at the bench's full size: the DEEP-shaped set (N = 1,000,000,
+d = 96, R = 32, leaf 1,024) and its whole batch of 100,000 queries in one
+launch, as bench.py times it; sampled outputs are checked one by one
+against the oracle (bit-exact ids and float32 distances)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_2504_04018_amd as esg  # noqa: E402
+
+DEV = torch.device("cuda:0")
+SAMPLE = 64
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def deep(tmp_path_factory):
+    w = synth.make_workload(2)
+    path = str(tmp_path_factory.mktemp("deep") / "deep1M.esgi")
+    print("[gpu] building the 1M x 96 index", flush=True)
+    esg.build_index(w["X"], w["attr"].astype(np.float64), path, degree=w["degree"],
+                    leaf=w["leaf"], ef_construction=w["ef_construction"])
+    del w["X"]
+    gix = esg.Index(path, 0)
+    gix.add_storage("bf16")
+    yield w, gix, path
+    gix.free()
+
+
+def _sample(nq, seed):
+    return np.sort(np.random.default_rng(seed).choice(nq, SAMPLE, replace=False))
+
+
+@pytest.mark.parametrize("trav,ef", [("f32", 22), ("bf16", 22)])
+def test_full_batch_sampled_parity(deep, trav, ef):
+    w, gix, path = deep
+    Q, l, r = w["Q"], w["l"], w["r"]
+    print(f"[gpu] full batch {len(Q)} queries {trav} ef={ef}", flush=True)
+    ids, dists = gix.search_ex(_t(Q), _t(l), _t(r), 10, ef, traversal=trav,
+                               rerank=trav != "f32")
+    torch.cuda.synchronize()
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    oix = oracle.read_index(path)
+    kind = oracle.DIST_F32
+    if trav == "bf16":
+        oix = oix.with_bf16()
+        kind = oracle.DIST_BF16
+    s = _sample(len(Q), 7 if trav == "f32" else 8)
+    oid, od, st = oracle.query_batch(oix, Q[s], l[s], r[s], 10, ef, ef, -1, kind,
+                                     int(trav != "f32"))
+    assert np.all(st == 0)
+    assert np.array_equal(ids[s], oid)
+    assert np.array_equal(dists[s].view(np.uint32), od.view(np.uint32))
+
+
+def test_full_batch_learned_sampled_parity(deep):
+    """The learned kernel over the whole batch (probe 4 hops at ef 32): the
+    oracle, given the beams the GPU chose, reproduces the sampled answers."""
+    w, gix, path = deep
+    Q, l, r = w["Q"], w["l"], w["r"]
+    nq = len(Q)
+    rng = np.random.default_rng(3)
+    p = np.concatenate([rng.standard_normal(5057) * 0.15, rng.standard_normal(12),
+                        np.abs(rng.standard_normal(12)) + 0.5]).astype(np.float32)
+    p[5056] = 4.0                                      # log2 beam around 4
+    feat = torch.full((nq, 2, 16), float("nan"), device=DEV)
+    print("[gpu] full batch learned", flush=True)
+    ids, dists = gix.search_ex(_t(Q), _t(l), _t(r), 10, 32, mlp=_t(p), probe_hops=4,
+                               feat_out=feat)
+    torch.cuda.synchronize()
+    ids, dists, F = ids.cpu().numpy(), dists.cpu().numpy(), feat.cpu().numpy()
+    oix = oracle.read_index(path)
+    switched = 0
+    for i in _sample(nq, 9):
+        ef2 = np.zeros(2, np.int32)
+        for j in range(2):
+            if not np.isnan(F[i, j, 0]):
+                ef2[j] = int(F[i, j, 13])
+                switched += 1
+        oid, od, _, st = oracle.query_learned(oix, Q[i], int(l[i]), int(r[i]), 10, 32, 4, ef2)
+        assert st == 0
+        assert np.array_equal(ids[i], oid), i
+        assert np.array_equal(dists[i].view(np.uint32), od.view(np.uint32)), i
+    assert switched > SAMPLE // 2
