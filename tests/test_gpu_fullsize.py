@@ -95,3 +95,43 @@ def test_full_batch_learned_sampled_parity(deep):
         assert np.array_equal(ids[i], oid), i
         assert np.array_equal(dists[i].view(np.uint32), od.view(np.uint32)), i
     assert switched > SAMPLE // 2
+
+
+@pytest.fixture(scope="module")
+def sift(tmp_path_factory):
+    w = synth.make_workload(1)
+    path = str(tmp_path_factory.mktemp("sift") / "sift1M.esgi")
+    print("[gpu] building the 1M x 128 index", flush=True)
+    esg.build_index(w["X"], w["attr"].astype(np.float64), path, degree=w["degree"],
+                    leaf=w["leaf"], ef_construction=w["ef_construction"])
+    del w["X"]
+    return w, path
+
+
+@pytest.mark.parametrize("trav", ["f32", "bf16"])
+def test_sift_full_size_sampled_parity(sift, trav):
+    """SIFT-shaped at full size (N = 1M, d = 128 uint8-valued, the 10,000
+    queries of 11 width buckets in one launch, ef 64): sampled queries
+    bit-exact against the oracle."""
+    w, path = sift
+    gix = esg.Index(path, 0)
+    if trav == "bf16":
+        gix.add_storage("bf16")
+    Q, l, r = w["Q"], w["l"], w["r"]
+    print(f"[gpu] sift full batch {trav}", flush=True)
+    ids, dists = gix.search_ex(_t(Q), _t(l), _t(r), 10, 64, traversal=trav,
+                               rerank=trav != "f32")
+    torch.cuda.synchronize()
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    gix.free()
+    oix = oracle.read_index(path)
+    kind = oracle.DIST_F32
+    if trav == "bf16":
+        oix = oix.with_bf16()
+        kind = oracle.DIST_BF16
+    s = _sample(len(Q), 11)
+    oid, od, st = oracle.query_batch(oix, Q[s], l[s], r[s], 10, 64, 64, -1, kind,
+                                     int(trav != "f32"))
+    assert np.all(st == 0)
+    assert np.array_equal(ids[s], oid)
+    assert np.array_equal(dists[s].view(np.uint32), od.view(np.uint32))
