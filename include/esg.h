@@ -186,8 +186,10 @@ typedef struct {
   const float* mlp;      /* device ESG_MLP_PARAMS floats, or NULL: the
                             learned beam width.  Each graph part runs
                             probe_hops expansions of Alg. 1 with m = ef
-                            (the largest beam), then the network maps 12
-                            features of the search state to y and the part
+                            (the largest beam); if its search goes on
+                            (the next candidate passes the stop test),
+                            the network maps 12 features of the search
+                            state to y and the part
                             continues with m = cand_cap = ef' =
                             clamp(ceil(2^(y + mlp_delta)), k, ef), keeping
                             the ef' best of P and Q.  Layout as for
@@ -205,7 +207,8 @@ typedef struct {
   float* feat_out;       /* device float [nq][2][16] or NULL: per graph part
                             the 12 features, y and ef' (or the granted
                             expansions when mlp_target = 1) (parts that end
-                            before the probe is over are left untouched)  */
+                            before or right at the end of the probe are
+                            left untouched)                               */
   esg_part_trace* trace; /* device [nq][2] or NULL                          */
   uint32_t* visited;     /* device [nq][2][visited_cap] or NULL: visited positions */
   int64_t visited_cap;   /* capacity per part of `visited`                  */

@@ -23,6 +23,8 @@ Contents and the passage each follows:
                              even; fp8 OCP E4M3 with a per-vector scale).
 * ``mlp_*``               -- float64 forward and manual backward of the
                              12-64-64-1 ReLU network that predicts ef.
+* ``adam_step64``         -- one Adam step (Kingma and Ba, Algorithm 1) in
+                             float64.
 """
 from __future__ import annotations
 
@@ -491,3 +493,28 @@ def mlp_grad64(params, F, T):
     gb1 = gA1.sum(0)
     grad = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3, gb3])
     return grad, float(np.mean(err ** 2))
+
+
+# --------------------------------------------------------------------------
+# Adam (Kingma and Ba, "Adam: A Method for Stochastic Optimization",
+# Algorithm 1) in float64.  The decay rates and epsilon are the float32
+# numbers nearest 0.9, 0.999 and 1e-8 (the optimizer's constants are float32
+# values); everything else is float64.
+# --------------------------------------------------------------------------
+
+ADAM_B1 = float(np.float32(0.9))
+ADAM_B2 = float(np.float32(0.999))
+ADAM_EPS = float(np.float32(1e-8))
+
+
+def adam_step64(theta, g, m, v, t, lr):
+    """Step t (>= 1): biased first and second moment estimates, their bias
+    corrections by 1 - beta^t, and the update theta - lr * mhat /
+    (sqrt(vhat) + eps).  Returns (theta, m, v) as new float64 arrays."""
+    theta, g = np.asarray(theta, np.float64), np.asarray(g, np.float64)
+    m, v = np.asarray(m, np.float64), np.asarray(v, np.float64)
+    m = ADAM_B1 * m + (1.0 - ADAM_B1) * g
+    v = ADAM_B2 * v + (1.0 - ADAM_B2) * g * g
+    mhat = m / (1.0 - ADAM_B1 ** t)
+    vhat = v / (1.0 - ADAM_B2 ** t)
+    return theta - float(lr) * mhat / (np.sqrt(vhat) + ADAM_EPS), m, v

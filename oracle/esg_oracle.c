@@ -303,10 +303,12 @@ static cand list_pop_min(sorted_list* l) {
  * q_dist/q_pos, the visited points (discovery order) to `visited` when it
  * is not NULL, and the number of expansions to *hops. */
 /* Learned beam width (not in the paper): when switch_hop >= 0 and the
- * search reaches switch_hop expansions, the features of the state are
- * written to feat (12 doubles, when not NULL) and, when ef2 > 0, P and Q
- * keep their ef2 best and the search continues with m = cap_p = ef2.
- * w_query and n_parts describe the whole query; k is the answer size. */
+ * search reaches switch_hop expansions and goes on (its next candidate
+ * passes the stop test of Alg. 1), the features of the state are written
+ * to feat (12 doubles, when not NULL) and, when ef2 > 0, P and Q keep
+ * their ef2 best and the search continues with m = cap_p = ef2.  A search
+ * that stops right there takes no switch.  w_query and n_parts describe
+ * the whole query; k is the answer size. */
 typedef struct {
   int64_t switch_hop;
   int32_t ef2;       /* > 0: new beam width */
@@ -318,8 +320,19 @@ typedef struct {
   int64_t hop2;      /* > 0: at most hop2 further expansions (stopping step) */
 } oracle_switch;
 
+/* The live part of P: candidates that can still be expanded, i.e. all of
+ * P while Q holds fewer than m results, else those not farther than the
+ * worst of Q (the stop bound only tightens, so the others never are). */
+static int64_t live_count(const sorted_list* P, const sorted_list* Q, int32_t m) {
+  if (Q->len < m) return P->len;
+  int64_t c = 0;
+  for (int64_t i = 0; i < P->len; i++)
+    if (!cand_less(Q->a[Q->len - 1], P->a[i])) c++;
+  return c;
+}
+
 static void probe_features(const oracle_switch* sw, const sorted_list* P, const sorted_list* Q,
-                           int64_t cap_p, int64_t a, int64_t b, int64_t x, int64_t y,
+                           int32_t m, int64_t cap_p, int64_t a, int64_t b, int64_t x, int64_t y,
                            double d_ep, int64_t n_inr, int64_t nv, double* f) {
   double wp = (double)(y - x + 1), L = (double)(b - a + 1);
   int64_t kk = sw->k < Q->len ? sw->k : Q->len;
@@ -333,7 +346,7 @@ static void probe_features(const oracle_switch* sw, const sorted_list* P, const 
   f[2] = wp / L;
   f[3] = log2((double)sw->w_query);
   f[4] = (double)(sw->n_parts - 1);
-  f[5] = (double)P->len / (double)cap_p;
+  f[5] = (double)live_count(P, Q, m) / (double)cap_p;
   f[6] = fill < 4.0 ? fill : 4.0;
   f[7] = (double)n_inr / (double)nv;
   f[8] = q0 / den;
@@ -392,9 +405,10 @@ int32_t oracle_search_part_sw(const oracle_index* ix, int32_t depth, int64_t hea
 
   int32_t status = OR_OK;
   while (P.len > 0) {
-    if (sw && sw->switch_hop >= 0 && h == sw->switch_hop) {
+    if (sw && sw->switch_hop >= 0 && h == sw->switch_hop &&
+        !(Q.len >= m && cand_less(Q.a[Q.len - 1], P.a[0]))) {
       if (sw->feat)
-        probe_features(sw, &P, &Q, cap_p, a, b, x, y, (double)e.dist, n_inr, nv, sw->feat);
+        probe_features(sw, &P, &Q, m, cap_p, a, b, x, y, (double)e.dist, n_inr, nv, sw->feat);
       if (sw->hop2 > 0 && (hop_budget < 0 || h + sw->hop2 < hop_budget))
         hop_budget = h + sw->hop2;                     /* stopping step */
       if (sw->ef2 > 0) {                               /* keep the ef2 best of P and Q */

@@ -167,7 +167,10 @@ int32_t esg_mlp_adam(float* params, const float* grad, float* m1, float* m2, int
                      float lr, void* stream) {
   if (!params || !grad || !m1 || !m2 || step < 1 || !(lr > 0.0f)) return ESG_EINVAL;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  // bias corrections 1 - beta^t in double: in float32 the subtraction
+  // cancels (1 - 0.999^2 keeps only about 3 significant digits)
+  const float c1 = (float)(1.0 - pow((double)b1, (double)step));
+  const float c2 = (float)(1.0 - pow((double)b2, (double)step));
   mlp_adam_kernel<<<(kMlpWeights + 255) / 256, 256, 0, static_cast<hipStream_t>(stream)>>>(
       params, grad, m1, m2, lr, b1, b2, eps, c1, c2);
   return hipGetLastError() == hipSuccess ? ESG_OK : ESG_EHIP;

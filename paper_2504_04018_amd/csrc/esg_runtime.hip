@@ -343,8 +343,8 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
   if (crc.update(0, &h, offsetof(esg::FileHeader, crc_header)) != h.crc_header) return ESG_EFORMAT;
   if (h.n <= 0 || h.n >= (int64_t)ESG_NO_NODE || h.d <= 0 || h.d > 65536 || h.degree < 1 ||
       h.degree > ESG_DEGREE_MAX || h.leaf < 1 || h.fanout != 2 || h.n_depth < 0 ||
-      h.n_depth > 40 || h.c_den < 1)
-    return ESG_EFORMAT;
+      h.n_depth > 40 || h.c_den < h.fanout)
+    return ESG_EFORMAT;   // c = 1/c_den <= 1/fanout keeps Alg. 4 at two parts at most
   const uint64_t sizes[5] = {esg::bytes_ids(h.n), esg::bytes_attr(h.n), esg::bytes_vec(h.n, h.d),
                              esg::bytes_adj(h.n, h.n_depth, h.degree), esg::bytes_ep(h.n_depth)};
   const uint64_t offs[5] = {h.off_ids, h.off_attr, h.off_vec, h.off_adj, h.off_ep};

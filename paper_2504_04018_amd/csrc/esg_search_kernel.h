@@ -87,7 +87,8 @@ __device__ __forceinline__ float mlp_infer(const float* __restrict__ P, float f,
 
 // Feature `lane` (lanes 0..11) of a graph part after the probe, from the
 // wave-uniform state: log2 of the part's filter width and node size, their
-// ratio, log2 of the query width, number of parts - 1, fill of P and of Q
+// ratio, log2 of the query width, number of parts - 1, fill of P's live part
+// and of Q
 // (relative to k, at most 4), in-range share of the visited points, the
 // best and k-th distances in Q and the best distance in P relative to the
 // entry's (or to the k-th), log2(1 + visited).
@@ -248,13 +249,18 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
     while (hop(true)) {
     }
   }
-  if (LEARN != 0 && go && u != kKeyInf && hops == A.probe_hops) {
+  // The switch is taken only when the search goes on past the probe (its
+  // next candidate passes the stop test); P's fill counts its live part
+  // (candidates not farther than a full Q's worst), which the lossless
+  // prune leaves unchanged.
+  const uint64_t worst0 = (LEARN != 0 && go) ? list_at(Q, m - 1) : kKeyInf;
+  if (LEARN != 0 && go && u != kKeyInf && hops == A.probe_hops && !(worst0 < u)) {
     // probe over: features -> predicted beam width or stopping step
     int qsize = 0, psize = 0;
 #pragma unroll
     for (int e = 0; e < E; e++) {
       qsize += __popcll(ballot(Q[e] != kKeyInf));
-      psize += __popcll(ballot(P[e] != kKeyInf));
+      psize += __popcll(ballot(P[e] != kKeyInf && P[e] <= worst0));
     }
     const int kk = A.k < qsize ? A.k : qsize;
     const float q0 = qsize > 0 ? key_dist(list_at(Q, 0)) : d_ep;

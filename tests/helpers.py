@@ -65,3 +65,26 @@ def make_test_index(X: np.ndarray, leaf: int, R: int = 8, ep_mode: str = "first"
     ext = np.arange(n, dtype=np.int64)
     return oracle.OracleIndex(n, d, R, leaf, n_depth, 2, ext, np.arange(n, dtype=np.float64),
                               X, adj, ep)
+
+
+def oracle_scan(oix, Q, l, r, k):
+    """The oracle's float32 linear scan of each query's whole range [l,r]
+    (top k by the canonical distance, ties by position): the exact answer
+    the brute-force scan must return.  Invalid ranges give -1 / +inf rows."""
+    ids = np.full((len(Q), k), -1, np.int64)
+    dists = np.full((len(Q), k), np.inf, np.float32)
+    L = oracle.lib()
+    for i in range(len(Q)):
+        if l[i] < 0 or r[i] >= oix.n or l[i] > r[i]:
+            continue
+        od = np.zeros(k, np.float32)
+        op = np.zeros(k, np.int64)
+        ol = np.zeros(1, np.int32)
+        q = np.ascontiguousarray(Q[i], np.float32)
+        st = L.oracle_scan_part(oix.cstruct(), int(l[i]), int(r[i]), q.ctypes.data, k,
+                                od.ctypes.data, op.ctypes.data, ol.ctypes.data)
+        assert st == 0
+        n = int(ol[0])
+        ids[i, :n] = oix.ext_id[op[:n]]
+        dists[i, :n] = od[:n]
+    return ids, dists

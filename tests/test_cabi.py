@@ -6,6 +6,7 @@ from __future__ import annotations
 import os
 import re
 import shutil
+import struct
 
 import numpy as np
 import pytest
@@ -93,6 +94,21 @@ def test_builder_errors(tmp_path):
     assert e.value.status == esg.ESG_EIO
 
 
+def _crc32c(data: bytes) -> int:
+    """CRC-32C (Castagnoli, reflected polynomial 0x82F63B78), bit by bit."""
+    crc = 0xFFFFFFFF
+    for byte in data:
+        crc ^= byte
+        for _ in range(8):
+            crc = (crc >> 1) ^ (0x82F63B78 if crc & 1 else 0)
+    return crc ^ 0xFFFFFFFF
+
+
+def test_crc32c_check_value():
+    # the standard check value of CRC-32C over the ASCII digits 1..9
+    assert _crc32c(b"123456789") == 0xE3069283
+
+
 def _load_status(path):
     import ctypes
     h = ctypes.c_void_p()
@@ -119,5 +135,13 @@ def test_loader_rejects_malformed(small_index, tmp_path):
     assert variant("crc", bad) == esg.ESG_EFORMAT
     bad = raw.copy(); bad[20] ^= 1                          # header field (n)
     assert variant("hdr", bad) == esg.ESG_EFORMAT
+    # c = 1 / c_den above 1 / fanout: Alg. 4 could select more than two parts
+    # (Lemma 4.2 needs c <= 1/2); a consistent header (checksum rewritten)
+    # with c_den = 1 must still be refused
+    bad = raw.copy()
+    assert struct.unpack_from("<i", bad, 44)[0] == 2        # c_den
+    struct.pack_into("<i", bad, 44, 1)
+    struct.pack_into("<I", bad, 124, _crc32c(bytes(bad[:124])))
+    assert variant("cden", bad) == esg.ESG_EFORMAT
     # a well-formed file: loads where a device exists, reports the missing device here
     assert _load_status(path) in (esg.ESG_OK, esg.ESG_EHIP)

@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 import synth
+from tests.helpers import oracle_scan
 
 pytestmark = pytest.mark.gpu
 
@@ -42,27 +43,6 @@ def idx(tmp_path_factory):
     oix = oracle.read_index(path)
     yield w, gix, oix
     gix.free()
-
-
-def oracle_scan(oix, Q, l, r, k):
-    ids = np.full((len(Q), k), -1, np.int64)
-    dists = np.full((len(Q), k), np.inf, np.float32)
-    for i in range(len(Q)):
-        if l[i] < 0 or r[i] >= oix.n or l[i] > r[i]:
-            continue
-        L = oracle.lib()
-        import ctypes
-        od = np.zeros(k, np.float32)
-        op = np.zeros(k, np.int64)
-        ol = np.zeros(1, np.int32)
-        q = np.ascontiguousarray(Q[i], np.float32)
-        st = L.oracle_scan_part(oix.cstruct(), int(l[i]), int(r[i]), q.ctypes.data, k,
-                                od.ctypes.data, op.ctypes.data, ol.ctypes.data)
-        assert st == 0
-        n = int(ol[0])
-        ids[i, :n] = oix.ext_id[op[:n]]
-        dists[i, :n] = od[:n]
-    return ids, dists
 
 
 def mixed_ranges(n, m, seed):

@@ -1,0 +1,88 @@
+"""GPU parity of the MFMA brute-force scan at the dimensions it serves.
+
+The scan forms bfloat16 dot products over 32-wide K chunks (d = 64, 96,
+128, 768 take 2, 3, 4 and 24 chunks), and its certificate bound grows with
+d.  At each of these dimensions, for range widths from 1 point to the whole
+set (many 2,048-position windows), its answer must equal the oracle's
+float32 scan of [l,r] bit for bit, whether a query was certified or
+rescanned exactly (and with every query forced through the exact path).
+The SIFT-shaped (uint8-valued) set at d = 128 has many exactly equal
+distances, so it also checks the (distance, position) tie-break.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import oracle_scan
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_2504_04018_amd as esg  # noqa: E402
+
+DEV = torch.device("cuda:0")
+NQ = 240
+
+# (workload law, d, N): DEEP-shaped unit-norm at d = 64 and 96, SIFT-shaped
+# uint8-valued at d = 128, embedding-shaped unit-norm at d = 768.
+SHAPES = [(2, 64, 20000), (2, 96, 20000), (1, 128, 20000), (3, 768, 6000)]
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.fixture(scope="module", params=SHAPES, ids=lambda s: f"d{s[1]}")
+def scan_idx(request, tmp_path_factory):
+    cid, d, n = request.param
+    w = synth.make_workload(cid, n=n, nq=NQ, d=d)
+    path = str(tmp_path_factory.mktemp(f"scan{d}") / "s.esgi")
+    esg.build_index(w["X"], w["attr"].astype(np.float64), path, degree=16, leaf=1024,
+                    ef_construction=32)
+    gix = esg.Index(path, 0)
+    gix.add_storage("bf16")
+    gix.reserve(NQ, 8192)
+    oix = oracle.read_index(path)
+    rng = np.random.default_rng(d)
+    wd = np.rint(np.exp(rng.uniform(0, np.log(n), NQ))).astype(np.int64)
+    wd[:4] = [1, 2, n, n - 1]
+    wd = np.clip(wd, 1, n)
+    l = (rng.random(NQ) * (n - wd + 1)).astype(np.int64)
+    r = l + wd - 1
+    yield w, gix, oix, l, r
+    gix.free()
+
+
+@pytest.mark.parametrize("k", [10, 100])
+def test_scan_certified_matches_oracle(scan_idx, k):
+    w, gix, oix, l, r = scan_idx
+    Q = w["Q"]
+    cert = torch.zeros(NQ, dtype=torch.int32, device=DEV)
+    print(f"[gpu] scan d={oix.d} k={k}", flush=True)
+    ids, dists, nfb = gix.scan(_t(Q), _t(l), _t(r), k, certified=cert)
+    torch.cuda.synchronize()
+    oid, od = oracle_scan(oix, Q, l, r, k)
+    assert np.array_equal(ids.cpu().numpy(), oid)
+    assert np.array_equal(dists.cpu().numpy().view(np.uint32), od.view(np.uint32))
+    c = cert.cpu().numpy()
+    print(f"d={oix.d} k={k}: certified {c.mean():.3f}, exact rescans {nfb}")
+    assert nfb == int((c == 0).sum())
+    assert c.mean() > 0.5
+
+
+def test_scan_forced_exact_matches_oracle(scan_idx):
+    w, gix, oix, l, r = scan_idx
+    Q = w["Q"]
+    print(f"[gpu] exact scan d={oix.d}", flush=True)
+    ids, dists, nfb = gix.scan(_t(Q), _t(l), _t(r), 10, exact=True)
+    torch.cuda.synchronize()
+    oid, od = oracle_scan(oix, Q, l, r, 10)
+    assert nfb == NQ
+    assert np.array_equal(ids.cpu().numpy(), oid)
+    assert np.array_equal(dists.cpu().numpy().view(np.uint32), od.view(np.uint32))

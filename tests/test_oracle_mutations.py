@@ -32,6 +32,12 @@ MUTATIONS = {
     # in-range share counted against |V| + 1
     "feature_inrange_share": ("f[7] = (double)n_inr / (double)nv;",
                               "f[7] = (double)n_inr / (double)(nv + 1);"),
+    # P's fill counted over the whole list instead of its live part
+    "feature_p_fill_raw": ("f[5] = (double)live_count(P, Q, m) / (double)cap_p;",
+                           "f[5] = (double)P->len / (double)cap_p;"),
+    # switch taken although the search stops right at the end of the probe
+    "switch_when_stopping": ("h == sw->switch_hop &&\n        !(Q.len >= m && cand_less(Q.a[Q.len - 1], P.a[0]))) {",
+                             "h == sw->switch_hop) {"),
     # split point rounded up
     "mid_rounded_up": ("int64_t mid = (a + b) / 2; /* a,b >= 0, so this is floor */",
                        "int64_t mid = (a + b + 1) / 2;"),

@@ -305,6 +305,45 @@ def test_learned_features_worked_example():
     assert p.tolist() == p0.tolist() and hops == h0
 
 
+def test_learned_features_live_part():
+    """P's fill counts only its live part, and no switch is taken when the
+    search stops right at the end of the probe.  Hand trace on a line,
+    q = 0, m = cap = 2, k = 2, node [0,4], query range [1,3]; positions
+    f=0 (x=10, out of range), e=1 (x=2, the entry), a=2 (x=3), g=3 (x=-4),
+    h=4 (x=5, out of range); edges e -> a, f; a -> g, h; f, g, h -> e.
+    Squared distances: e 4, a 9, g 16, h 25, f 100.
+    After one expansion (of e): V = {e, a, f}, P = {a 9, f 100},
+    Q = {e 4, a 9} (full, worst 9).  The next candidate a (9) is not
+    farther than the worst, so the search goes on and the features are
+    taken; f (100) is farther than the worst of a full Q and can never be
+    expanded, so the live fill of P is 1/2.
+    After two expansions (a's neighbours g 16 and h 25 both lose to the
+    full Q): P = {g 16, h 25}, whose best is farther than the worst (9):
+    the search stops, so no features are taken."""
+    X = np.array([[10.0], [2.0], [3.0], [-4.0], [5.0]], np.float32)
+    adj = np.full((1, 5, 2), 0xFFFFFFFF, np.uint32)
+    adj[0, 1] = [2, 0]
+    adj[0, 2] = [3, 4]
+    adj[0, 0, 0] = adj[0, 3, 0] = adj[0, 4, 0] = 1
+    ep = np.array([0xFFFFFFFF, 1], np.uint32)
+    ix = oracle.OracleIndex(5, 1, 2, 1, 1, 2, np.arange(5), np.arange(5.0), X, adj, ep)
+    part = dict(depth=0, heap=1, a=0, b=4, x=1, y=3)
+    q = np.zeros(1, np.float32)
+    d, p, vis, hops, st, f = oracle.search_part_learned(ix, part, q, ef_max=2, switch_hop=1,
+                                                        ef2=0, k=2, w_query=3, n_parts=1)
+    assert st == 0 and f is not None
+    want = [np.log2(3), np.log2(5), 3 / 5, np.log2(3), 0.0,
+            1 / 2,                                 # live part of P: a only
+            1.0, 2 / 3,                            # Q fill over k, in-range share of V
+            4 / 4, 9 / 4, 9 / 9,                   # best and k-th in Q, best in P
+            np.log2(1 + 3)]
+    assert np.allclose(f, want, rtol=0, atol=1e-12), (f, want)
+    assert p.tolist() == [1, 2] and hops == 2 and vis.tolist() == [1, 2, 0, 3, 4]
+    d, p, vis, hops, st, f = oracle.search_part_learned(ix, part, q, ef_max=2, switch_hop=2,
+                                                        ef2=0, k=2, w_query=3, n_parts=1)
+    assert st == 0 and f is None and hops == 2
+
+
 def test_post_short_q_keeps_searching():
     """Alg. 1 stop test read with a full-Q guard: under POST, Q holds only
     in-range points, so it may be short of m while an out-of-range
@@ -562,3 +601,56 @@ def test_mlp_backprop_matches_finite_differences():
         e[j] = h
         fd = (L(params + e) - L(params - e)) / (2 * h)
         assert abs(fd - grad[j]) <= 1e-6 + 1e-5 * abs(fd), (j, fd, grad[j])
+
+
+# ---------------------------------------------------------------- Adam
+
+def test_adam_first_step_is_sign_step():
+    """Step 1 from zero moments: both bias corrections cancel the (1 - beta)
+    factors exactly, so the update is lr * g / (|g| + eps): lr times the
+    sign of g wherever |g| >> eps.  A wrong or missing bias correction
+    scales it by (1 - beta1) / sqrt(1 - beta2) or its inverse."""
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal(500) * np.exp(rng.uniform(-8, 4, 500))
+    theta = rng.standard_normal(500)
+    lr = 1e-3
+    t1, m, v = oracle.adam_step64(theta, g, np.zeros(500), np.zeros(500), 1, lr)
+    assert np.allclose(theta - t1, lr * g / (np.abs(g) + oracle.ADAM_EPS), rtol=1e-12, atol=0)
+    assert np.allclose(m, (1 - oracle.ADAM_B1) * g, rtol=1e-15)
+    assert np.allclose(v, (1 - oracle.ADAM_B2) * g * g, rtol=1e-15)
+
+
+def test_adam_constant_gradient_keeps_its_step():
+    """With the same gradient at every step from zero moments, the biased
+    moments are (1 - beta^t) g and (1 - beta^t) g^2, so the bias-corrected
+    ones are exactly g and g^2 and every step moves by lr * g / (|g| + eps)
+    (Kingma and Ba, Section 3: the correction removes the initialisation
+    bias).  A wrong decay rate or exponent in the correction drifts."""
+    rng = np.random.default_rng(12)
+    g = rng.standard_normal(300)
+    theta = rng.standard_normal(300)
+    m = np.zeros(300)
+    v = np.zeros(300)
+    lr = 2e-3
+    step = lr * g / (np.abs(g) + oracle.ADAM_EPS)
+    for t in range(1, 60):
+        t1, m, v = oracle.adam_step64(theta, g, m, v, t, lr)
+        assert np.allclose(theta - t1, step, rtol=1e-9, atol=0), t
+        theta = t1
+    assert np.allclose(m, (1 - oracle.ADAM_B1 ** 59) * g, rtol=1e-12)
+
+
+def test_adam_zero_gradient_after_one_step():
+    """After a step with g, a zero gradient at step 2 leaves
+    m = beta1 (1 - beta1) g and v = beta2 (1 - beta2) g^2, so the second
+    update is lr * [beta1 (1-beta1) g / (1-beta1^2)] /
+    (sqrt(beta2 (1-beta2) g^2 / (1-beta2^2)) + eps), worked from the
+    definitions: the momentum keeps moving the point."""
+    b1, b2, eps = oracle.ADAM_B1, oracle.ADAM_B2, oracle.ADAM_EPS
+    g = np.array([0.5, -2.0, 1e-3])
+    theta = np.zeros(3)
+    t1, m, v = oracle.adam_step64(theta, g, np.zeros(3), np.zeros(3), 1, 0.01)
+    t2, m, v = oracle.adam_step64(t1, np.zeros(3), m, v, 2, 0.01)
+    mh = b1 * (1 - b1) * g / (1 - b1 ** 2)
+    vh = b2 * (1 - b2) * g * g / (1 - b2 ** 2)
+    assert np.allclose(t1 - t2, 0.01 * mh / (np.sqrt(vh) + eps), rtol=1e-12)
