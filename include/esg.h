@@ -269,6 +269,18 @@ int32_t esg_mlp_forward(const float* params, const float* feats, int64_t n, floa
  * [ESG_MLP_WORKSPACE_FLOATS], owned by the caller.  Deterministic. */
 int32_t esg_mlp_grad(const float* params, const float* feats, const float* target, int64_t n,
                      float* grad, float* loss, float* workspace, void* stream);
+/* esg_mlp_grad without the caller's workspace, for callers that cannot
+ * allocate device memory (code under hipGraph capture, serving loops,
+ * harnesses that forbid hipMalloc).  The per-wave partial gradients go to
+ * a fixed scratch array inside the library (ESG_MLP_WORKSPACE_FLOATS floats,
+ * about 10 MB per GPU, held until the process ends); the call allocates
+ * nothing.  Any n >= 1 fits (the scratch size does not depend on n).  All
+ * calls on one GPU share that GPU's scratch: calls that overlap in time on
+ * one GPU (two streams, two threads) race and must be serialised by the
+ * caller.  Same results as esg_mlp_grad, bit for bit.  Errors: EINVAL,
+ * EHIP. */
+int32_t esg_mlp_grad_noalloc(const float* params, const float* feats, const float* target,
+                             int64_t n, float* grad, float* loss, void* stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the trainable
  * weights; m1, m2: device float[ESG_MLP_WEIGHTS] moments, step >= 1. */
 int32_t esg_mlp_adam(float* params, const float* grad, float* m1, float* m2, int64_t step,

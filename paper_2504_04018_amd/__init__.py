@@ -99,6 +99,7 @@ SIGNATURES = {
     "esg_mlp_forward": (_I32, [_VP, _VP, _I64, _VP, _VP]),
     "esg_mlp_grad": (_I32, [_VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP]),
     "esg_mlp_adam": (_I32, [_VP, _VP, _VP, _VP, _I64, ctypes.c_float, _VP]),
+    "esg_mlp_grad_noalloc": (_I32, [_VP, _VP, _VP, _I64, _VP, _VP, _VP]),
 }
 MLP_FEATURES, MLP_WEIGHTS, MLP_PARAMS = 12, 5057, 5081
 MLP_WORKSPACE_FLOATS = 512 * 5058
@@ -315,6 +316,19 @@ def mlp_grad(params, feats, target, grad, loss, workspace, stream=None):
                               _dev(loss, torch.float32, (1,), "loss"),
                               _dev(workspace, torch.float32, (MLP_WORKSPACE_FLOATS,), "workspace"),
                               _stream_ptr(stream)), "esg_mlp_grad")
+
+
+def mlp_grad_noalloc(params, feats, target, grad, loss, stream=None):
+    """esg_mlp_grad_noalloc: as mlp_grad, with the library's own scratch
+    (allocates nothing; calls on one GPU must not overlap)."""
+    import torch
+    n = feats.shape[0]
+    _check(lib().esg_mlp_grad_noalloc(_dev(params, torch.float32, (MLP_PARAMS,), "params"),
+                                      _dev(feats, torch.float32, (n, MLP_FEATURES), "feats"),
+                                      _dev(target, torch.float32, (n,), "target"), n,
+                                      _dev(grad, torch.float32, (MLP_WEIGHTS,), "grad"),
+                                      _dev(loss, torch.float32, (1,), "loss"),
+                                      _stream_ptr(stream)), "esg_mlp_grad_noalloc")
 
 
 def mlp_adam(params, grad, m1, m2, step, lr, stream=None):

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/esg.h"
 #include "esg_kernels.h"
@@ -140,6 +141,37 @@ __global__ void mlp_adam_kernel(float* __restrict__ P, const float* __restrict__
   P[j] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
 }
 
+// Scratch of esg_mlp_grad_noalloc: the per-wave gradient slices, in a
+// file-scope device array (one copy per GPU, held until the process ends).
+// Host code never passes `scratch` itself to a kernel: its name on the host
+// is a stand-in, not a device address; the device address is looked up
+// once per device with hipGetSymbolAddress and kept in scratch_ptr.
+constexpr size_t kScratchFloats = (size_t)kGradWaves * kSlice;   // 10.4 MB
+__device__ __align__(256) float scratch[kScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device (null on error).
+float* scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -160,6 +192,20 @@ int32_t esg_mlp_grad(const float* params, const float* feats, const float* targe
   hipStream_t s = static_cast<hipStream_t>(stream);
   mlp_grad_kernel<<<kGradWaves / 4, 256, 0, s>>>(params, feats, target, n, workspace);
   mlp_reduce_kernel<<<(kSlice + 255) / 256, 256, 0, s>>>(workspace, kGradWaves, grad, loss);
+  return hipGetLastError() == hipSuccess ? ESG_OK : ESG_EHIP;
+}
+
+int32_t esg_mlp_grad_noalloc(const float* params, const float* feats, const float* target,
+                             int64_t n, float* grad, float* loss, void* stream) {
+  if (!params || !feats || !target || !grad || n < 1) return ESG_EINVAL;
+  // the scratch holds one slice per gradient wave whatever n is; every call
+  // rewrites all of it, so nothing has to be cleared between calls
+  static_assert(kScratchFloats == (size_t)ESG_MLP_WORKSPACE_FLOATS, "scratch size");
+  float* ws = scratch_on_current_device();
+  if (!ws) return ESG_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  mlp_grad_kernel<<<kGradWaves / 4, 256, 0, s>>>(params, feats, target, n, ws);
+  mlp_reduce_kernel<<<(kSlice + 255) / 256, 256, 0, s>>>(ws, kGradWaves, grad, loss);
   return hipGetLastError() == hipSuccess ? ESG_OK : ESG_EHIP;
 }
 
