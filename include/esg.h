@@ -10,11 +10,14 @@
  * (approximate) k points nearest to q in Euclidean distance (Def. 2.1)
  * among the positions l <= p <= r.
  *
- * Index (Section 4.2, HBI-2D): a fanout-2 segment tree over [0, N-1].  Node
- * [a,b] is split at floor((a+b)/2); a node with b - a >= leaf holds a
- * proximity graph over its points (Alg. 3); smaller nodes are scanned.
- * A query picks at most two nodes (Alg. 4, Lemma 4.2) whose graphs cover
- * [l,r] with ratio |part| / |node| >= 1/2 (Def. 3.1), searches each with
+ * Index (Section 4.2, HBI-2D): a segment tree of fanout f over [0, N-1]
+ * (f = 2 in Alg. 3/4; larger f is the extension of Section 4.2).  Node
+ * [a,b] of L points has children j = 0..f-1 = [a + ceil(jL/f),
+ * a + ceil((j+1)L/f) - 1] (at f = 2: split at floor((a+b)/2)); a node with
+ * b - a >= leaf holds a proximity graph over its points (Alg. 3); smaller
+ * nodes are scanned.  A query picks at most two nodes (Alg. 4, Lemma 4.2,
+ * Lemma 4.3) whose graphs cover [l,r] with ratio |part| / |node| >= 1/f
+ * (Def. 3.1 with the elastic constant c = 1/f), searches each with
  * Alg. 1 under the POST principle (Section 2.2) -- out-of-range points are
  * traversed but never returned -- and merges the two answers.
  *
@@ -50,6 +53,7 @@ extern "C" {
 
 #define ESG_EF_MAX 1024      /* largest beam width m (= ef) accepted        */
 #define ESG_DEGREE_MAX 32    /* largest graph degree accepted               */
+#define ESG_FANOUT_MAX 64    /* largest segment-tree fanout accepted        */
 #define ESG_NO_NODE 0xFFFFFFFFu /* padding value of an adjacency row        */
 
 /* ---- index file (version 1), little-endian ------------------------------
@@ -67,16 +71,21 @@ extern "C" {
  *   adj  uint32 [n_depth][n][degree]  row p of depth t: neighbours of p in
  *                                  the graph of the depth-t node holding p,
  *                                  positions inside that node, ESG_NO_NODE pad
- *   ep   uint32 [2^n_depth]        entry point of the graph node with heap
- *                                  number h (root 1, children 2h and 2h+1),
- *                                  ESG_NO_NODE where the node has no graph
+ *   ep   uint32 [1 + sum_{t<n_depth} fanout^t]  entry point of the tree
+ *                                  node numbered h: root 1, child j of node h
+ *                                  numbered fanout*(h-1) + 2 + j (2h, 2h+1 at
+ *                                  fanout 2); ESG_NO_NODE where the node has
+ *                                  no graph
+ * c_den is the elastic constant's denominator (c = 1/c_den); the builder
+ * writes c_den = fanout and the loader requires c_den >= fanout.
  * ----------------------------------------------------------------------- */
 
 typedef struct {
   int32_t degree;          /* max out-degree R of every graph (<= 32), 16   */
   int32_t leaf;            /* leaf bound: node [a,b] has a graph iff b-a >= leaf (>= 1) */
   int32_t ef_construction; /* beam width of the insertion searches, 200     */
-  int32_t fanout;          /* segment-tree fanout; only 2 is supported      */
+  int32_t fanout;          /* segment-tree fanout f in [2, ESG_FANOUT_MAX]
+                              (0 = 2); the elastic constant is c = 1/f    */
   int32_t threads;         /* host threads, 0 = all                         */
   int32_t batch_max;       /* largest insertion batch, 0 = default (1024)   */
   int32_t verbose;         /* print progress to stderr                      */
@@ -86,14 +95,17 @@ typedef struct {
 /* Builds the HBI-2D index of Alg. 3 on the host and writes it to out_path.
  * vecs: host float32 [n][d] row-major, point i = external id i.
  * attr: host float64 [n] attribute values (any order; equal values are
- *       ranked by external id).
- * Each internal node's graph is a copy of its left child's graph plus the
- * insertion of the right half (Alg. 3); a node whose left child is a leaf
- * first builds the left half from scratch.  Insertion is a beam search of
+ *       ranked by external id).  The library ranks them itself, so
+ *       positions are attribute ranks (ties by external id).
+ * Each internal node's graph is a copy of its first child's graph plus the
+ * insertion of its other points (Alg. 3; at fanout 2 the right half); a
+ * node whose first child is a leaf first builds that child's points from
+ * scratch.  Insertion is a beam search of
  * width ef_construction followed by occlusion pruning (Section 2.1) to at
  * most `degree` neighbours and reverse edges.  Points are inserted in
  * deterministic batches, so the file does not depend on `threads`.
- * Errors: EINVAL (null/size), ENOMEM, EIO. */
+ * Errors: EINVAL (null/size), EUNSUPPORTED (fanout > ESG_FANOUT_MAX),
+ * ERANGE (tree too deep), ENOMEM, EIO. */
 int32_t esg_build_index(const float* vecs, const double* attr, int64_t n, int32_t d,
                         const esg_build_params* params, const char* out_path);
 

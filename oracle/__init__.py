@@ -71,7 +71,7 @@ def lib():
 class _Index(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("r", ctypes.c_int32),
                 ("n_depth", ctypes.c_int32), ("leaf", ctypes.c_int32), ("c_den", ctypes.c_int32),
-                ("pad_", ctypes.c_int32),
+                ("fanout", ctypes.c_int32),
                 ("vec", ctypes.c_void_p), ("vec16", ctypes.c_void_p), ("vec8", ctypes.c_void_p),
                 ("scale8", ctypes.c_void_p), ("adj", ctypes.c_void_p), ("ep", ctypes.c_void_p),
                 ("ext_id", ctypes.c_void_p)]
@@ -79,11 +79,11 @@ class _Index(ctypes.Structure):
 
 def _declare(L):
     i64, i32, vp, f32 = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_float
-    L.oracle_select.argtypes = [i64, i64, i32, i64, i64, vp, i32]
+    L.oracle_select.argtypes = [i64, i64, i32, i32, i64, i64, vp, i32]
     L.oracle_select.restype = i32
     L.oracle_elastic_ok.argtypes = [i64, i64, i64, i64, i32]
     L.oracle_elastic_ok.restype = i32
-    L.oracle_elastic_factor.argtypes = [i64, i64, i64, i64, vp, vp]
+    L.oracle_elastic_factor.argtypes = [i64, i64, i32, i64, i64, vp, vp]
     L.oracle_elastic_factor.restype = i32
     L.oracle_cd32.argtypes = [vp, vp, i32]
     L.oracle_cd32.restype = f32
@@ -126,9 +126,9 @@ def _p(a: np.ndarray | None):
 class OracleIndex:
     """Arrays of one index in host memory plus the C view the oracle uses."""
 
-    def __init__(self, n, d, degree, leaf, n_depth, c_den, ext_id, attr, vec, adj, ep):
+    def __init__(self, n, d, degree, leaf, n_depth, c_den, ext_id, attr, vec, adj, ep, fanout=2):
         self.n, self.d, self.degree, self.leaf = int(n), int(d), int(degree), int(leaf)
-        self.n_depth, self.c_den = int(n_depth), int(c_den)
+        self.n_depth, self.c_den, self.fanout = int(n_depth), int(c_den), int(fanout)
         self.ext_id = np.ascontiguousarray(ext_id, dtype=np.int64)
         self.attr = np.ascontiguousarray(attr, dtype=np.float64)
         self.vec = np.ascontiguousarray(vec, dtype=np.float32)
@@ -138,6 +138,10 @@ class OracleIndex:
         self.vec8 = None
         self.scale8 = None
         self._c = None
+
+    def select(self, lq: int, rq: int):
+        """Alg. 4 on this index's tree (its leaf bound, fanout and c)."""
+        return select(self.n, self.leaf, int(lq), int(rq), c_den=self.c_den, fanout=self.fanout)
 
     def with_bf16(self):
         self.vec16 = bf16_encode(self.vec)
@@ -153,7 +157,7 @@ class OracleIndex:
         if self._c is None:
             s = _Index()
             s.n, s.d, s.r, s.n_depth = self.n, self.d, self.degree, self.n_depth
-            s.leaf, s.c_den, s.pad_ = self.leaf, self.c_den, 0
+            s.leaf, s.c_den, s.fanout = self.leaf, self.c_den, self.fanout
             s.vec, s.vec16, s.vec8 = _p(self.vec), _p(self.vec16), _p(self.vec8)
             s.scale8, s.adj, s.ep, s.ext_id = _p(self.scale8), _p(self.adj), _p(self.ep), _p(self.ext_id)
             self._c = s
@@ -169,7 +173,7 @@ def read_index(path: str) -> OracleIndex:
     n, = struct.unpack_from("<q", head, 16)
     d, degree, leaf, fanout, n_depth, c_den, efc, _ = struct.unpack_from("<8i", head, 24)
     off_ids, off_attr, off_vec, off_adj, off_ep, file_bytes = struct.unpack_from("<6Q", head, 56)
-    if version != 1 or fanout != 2:
+    if version != 1 or fanout < 2:
         raise ValueError("unsupported index version/fanout")
     mm = np.memmap(path, dtype=np.uint8, mode="r")
     if mm.size != file_bytes:
@@ -182,8 +186,15 @@ def read_index(path: str) -> OracleIndex:
     attr = sect(off_attr, np.float64, n)
     vec = sect(off_vec, np.float32, n * d).reshape(n, d)
     adj = sect(off_adj, np.uint32, n_depth * n * degree).reshape(n_depth, n, degree)
-    ep = sect(off_ep, np.uint32, 1 << n_depth)
-    return OracleIndex(n, d, degree, leaf, n_depth, c_den, ext_id, attr, vec, adj, ep)
+    ep = sect(off_ep, np.uint32, node_numbers(fanout, n_depth))
+    return OracleIndex(n, d, degree, leaf, n_depth, c_den, ext_id, attr, vec, adj, ep, fanout)
+
+
+def node_numbers(fanout: int, n_depth: int) -> int:
+    """Length of the entry-point table: node numbers 1 .. sum of fanout^t
+    over the depths t < n_depth (breadth-first from the root 1), plus the
+    unused 0."""
+    return 1 + sum(fanout ** t for t in range(n_depth))
 
 
 # --------------------------------------------------------------------------
@@ -265,20 +276,22 @@ def e4m3_encode_rows(x: np.ndarray):
 # Wrappers.
 # --------------------------------------------------------------------------
 
-def select(n: int, leaf: int, lq: int, rq: int, c_den: int = 2, max_parts: int = 64):
-    """Alg. 4 parts as a list of dicts (kind, depth, heap, a, b, x, y)."""
+def select(n: int, leaf: int, lq: int, rq: int, c_den: int = 2, max_parts: int = 64,
+           fanout: int = 2):
+    """Alg. 4 parts as a list of dicts (kind, depth, heap, a, b, x, y) for a
+    tree of the given fanout (elastic constant c = 1/c_den)."""
     buf = np.zeros((max_parts, 7), dtype=np.int64)
-    cnt = lib().oracle_select(n, leaf, c_den, lq, rq, _p(buf), max_parts)
+    cnt = lib().oracle_select(n, leaf, c_den, fanout, lq, rq, _p(buf), max_parts)
     if cnt < 0:
         raise ValueError(f"invalid range [{lq},{rq}] for n={n}")
     keys = ("kind", "depth", "heap", "a", "b", "x", "y")
     return [dict(zip(keys, map(int, buf[i]))) for i in range(min(cnt, max_parts))], cnt
 
 
-def elastic_factor(n: int, leaf: int, l: int, r: int):
+def elastic_factor(n: int, leaf: int, l: int, r: int, fanout: int = 2):
     num = np.zeros(1, np.int64)
     den = np.zeros(1, np.int64)
-    st = lib().oracle_elastic_factor(n, leaf, l, r, _p(num), _p(den))
+    st = lib().oracle_elastic_factor(n, leaf, fanout, l, r, _p(num), _p(den))
     if st != 0:
         raise ValueError("bad range")
     return int(num[0]), int(den[0])

@@ -9,7 +9,8 @@
  *
  * What each function follows:
  *   oracle_select        Alg. 4 (Query-2D-Index) recursion, Section 4.2, with
- *                        the elastic test of Def. 3.1 at c = 1/c_den.
+ *                        the elastic test of Def. 3.1 at c = 1/c_den, for a
+ *                        segment tree of fanout f (Section 4.2, Extensions).
  *   oracle_elastic_ok    Def. 3.1 test |[x,y]| / |[a,b]| >= c, in integers.
  *   oracle_cd32/16/8     squared Euclidean distance (Section 2.1) in float32
  *                        with a fixed summation order, see below.
@@ -22,6 +23,11 @@
  *
  * Readings where the paper is silent (each also listed in the design notes):
  *   - Positions are 0-based ranks; the paper's [1,N] shifted by one.
+ *   - Fanout f: node [a,b] of L = b-a+1 points has children
+ *     j = 0..f-1 = [a + ceil(j L / f), a + ceil((j+1) L / f) - 1] (empty when
+ *     the bounds cross).  At f = 2 this is Alg. 3/4's split at
+ *     floor((a+b)/2).  Nodes are numbered breadth-first from the root 1;
+ *     child j of node h is f (h - 1) + 2 + j (2h and 2h+1 at f = 2).
  *   - Order: every comparison uses the pair (distance, position),
  *     lexicographically, so no two candidates ever tie.
  *   - Alg. 1's stop test compares against the worst result only once Q holds
@@ -73,13 +79,13 @@ typedef struct {
   int32_t n_depth;        /* tree depths that hold at least one graph */
   int32_t leaf;           /* leaf bound: node [a,b] has a graph iff b-a >= leaf */
   int32_t c_den;          /* elastic constant c = 1/c_den */
-  int32_t pad_;
+  int32_t fanout;         /* children per tree node */
   const float* vec;       /* [n][d] float32 in position order */
   const uint16_t* vec16;  /* [n][d] bfloat16 bit patterns, or NULL */
   const uint8_t* vec8;    /* [n][d] fp8 e4m3 codes, or NULL */
   const float* scale8;    /* [n] per-vector fp8 scale, or NULL */
   const uint32_t* adj;    /* [n_depth][n][r] neighbour positions, NO_NODE pad */
-  const uint32_t* ep;     /* [2^n_depth] entry point by heap index (root = 1) */
+  const uint32_t* ep;     /* entry point by node number (root = 1) */
   const int64_t* ext_id;  /* [n] external id of each position */
 } oracle_index;
 
@@ -93,12 +99,18 @@ int32_t oracle_elastic_ok(int64_t a, int64_t b, int64_t x, int64_t y, int32_t c_
   return (int64_t)c_den * (y - x + 1) >= (b - a + 1);
 }
 
+/* First position of child j of the node starting at a with L points. */
+static int64_t child_start(int64_t a, int64_t L, int32_t f, int64_t j) {
+  return a + (j * L + f - 1) / f;
+}
+
 typedef struct {
   int64_t* out;  /* [max_parts][7]: kind, depth, heap, a, b, x, y */
   int32_t max_parts;
   int32_t n_parts;
   int64_t leaf;
   int32_t c_den;
+  int32_t fanout;
 } select_ctx;
 
 static void emit_part(select_ctx* s, int64_t kind, int64_t depth, int64_t heap,
@@ -123,26 +135,32 @@ static void query2d(select_ctx* s, int64_t a, int64_t b, int64_t depth, int64_t 
     emit_part(s, KIND_GRAPH, depth, heap, a, b, x, y);
     return;
   }
-  int64_t mid = (a + b) / 2; /* a,b >= 0, so this is floor */
-  if (x <= mid) query2d(s, a, mid, depth + 1, 2 * heap, x, y < mid ? y : mid);
-  if (y > mid) query2d(s, mid + 1, b, depth + 1, 2 * heap + 1, x > mid + 1 ? x : mid + 1, y);
+  /* split into the f children; recurse into each one the query touches */
+  int64_t L = b - a + 1;
+  for (int64_t j = 0; j < s->fanout; j++) {
+    int64_t ca = child_start(a, L, s->fanout, j), cb = child_start(a, L, s->fanout, j + 1) - 1;
+    if (ca > cb || y < ca || x > cb) continue;
+    query2d(s, ca, cb, depth + 1, (int64_t)s->fanout * (heap - 1) + 2 + j,
+            x > ca ? x : ca, y < cb ? y : cb);
+  }
 }
 
 /* Returns the number of parts (may exceed max_parts: only the first
  * max_parts are written), or OR_EINVAL for a bad range. */
-int32_t oracle_select(int64_t n, int64_t leaf, int32_t c_den, int64_t lq, int64_t rq,
-                      int64_t* parts, int32_t max_parts) {
-  if (n <= 0 || leaf < 0 || c_den < 1 || lq < 0 || rq >= n || lq > rq) return OR_EINVAL;
-  select_ctx s = {parts, max_parts, 0, leaf, c_den};
+int32_t oracle_select(int64_t n, int64_t leaf, int32_t c_den, int32_t fanout, int64_t lq,
+                      int64_t rq, int64_t* parts, int32_t max_parts) {
+  if (n <= 0 || leaf < 0 || c_den < 1 || fanout < 2 || lq < 0 || rq >= n || lq > rq)
+    return OR_EINVAL;
+  select_ctx s = {parts, max_parts, 0, leaf, c_den, fanout};
   query2d(&s, 0, n - 1, 0, 1, lq, rq);
   return s.n_parts;
 }
 
 /* Elastic factor e(R,[l,r]) of Def. 3.1 over the set R of all graph nodes
- * of the fanout-2 segment tree on [0,n-1]: the largest |[l,r]| / |[a,b]|
+ * of the fanout-f segment tree on [0,n-1]: the largest |[l,r]| / |[a,b]|
  * over recorded supersets [a,b].  Returned as the pair (num, den) of the
  * best ratio; den = 0 when no recorded node contains [l,r]. */
-static void elastic_walk(int64_t a, int64_t b, int64_t leaf, int64_t l, int64_t r,
+static void elastic_walk(int64_t a, int64_t b, int64_t leaf, int32_t f, int64_t l, int64_t r,
                          int64_t* best_num, int64_t* best_den) {
   if (b - a < leaf) return;          /* not a recorded range, nor are its children */
   if (!(a <= l && r <= b)) return;   /* not a superset */
@@ -150,16 +168,17 @@ static void elastic_walk(int64_t a, int64_t b, int64_t leaf, int64_t l, int64_t 
   if (*best_den == 0 || num * (*best_den) > (*best_num) * den) {
     *best_num = num; *best_den = den;
   }
-  int64_t mid = (a + b) / 2;
-  elastic_walk(a, mid, leaf, l, r, best_num, best_den);
-  elastic_walk(mid + 1, b, leaf, l, r, best_num, best_den);
+  for (int64_t j = 0; j < f; j++) {
+    int64_t ca = child_start(a, den, f, j), cb = child_start(a, den, f, j + 1) - 1;
+    if (ca <= cb) elastic_walk(ca, cb, leaf, f, l, r, best_num, best_den);
+  }
 }
 
-int32_t oracle_elastic_factor(int64_t n, int64_t leaf, int64_t l, int64_t r,
+int32_t oracle_elastic_factor(int64_t n, int64_t leaf, int32_t fanout, int64_t l, int64_t r,
                               int64_t* num, int64_t* den) {
-  if (n <= 0 || l < 0 || r >= n || l > r) return OR_EINVAL;
+  if (n <= 0 || fanout < 2 || l < 0 || r >= n || l > r) return OR_EINVAL;
   *num = 0; *den = 0;
-  elastic_walk(0, n - 1, leaf, l, r, num, den);
+  elastic_walk(0, n - 1, leaf, fanout, l, r, num, den);
   return OR_OK;
 }
 
@@ -380,7 +399,9 @@ int32_t oracle_search_part_sw(const oracle_index* ix, int32_t depth, int64_t hea
                               int64_t* hops, const oracle_switch* sw) {
   if (m < 1 || cap_p < 1 || depth < 0 || depth >= ix->n_depth) return OR_EINVAL;
   if (!(0 <= a && a <= x && x <= y && y <= b && b < ix->n)) return OR_EINVAL;
-  if (heap < 1 || heap >= ((int64_t)1 << ix->n_depth)) return OR_EINVAL;
+  int64_t n_heap = 1, level = 1;                  /* node numbers of depths < n_depth */
+  for (int32_t t = 0; t < ix->n_depth; t++) { n_heap += level; level *= ix->fanout; }
+  if (heap < 1 || heap >= n_heap) return OR_EINVAL;
   uint32_t ep = ix->ep[heap];
   if (ep == NO_NODE || (int64_t)ep < a || (int64_t)ep > b) return OR_EGRAPH;
   const uint32_t* rows = ix->adj + (int64_t)depth * ix->n * ix->r;
@@ -510,7 +531,7 @@ int32_t oracle_query_sw(const oracle_index* ix, const float* q, int64_t lq, int6
   if (stats) memset(stats, 0, sizeof(int64_t) * 8);
   if (k < 1 || ef < k) return OR_EINVAL;
   int64_t parts[MAX_PARTS * 7];
-  int32_t np = oracle_select(ix->n, ix->leaf, ix->c_den, lq, rq, parts, MAX_PARTS);
+  int32_t np = oracle_select(ix->n, ix->leaf, ix->c_den, ix->fanout, lq, rq, parts, MAX_PARTS);
   if (np < 0) return np;
   if (np > MAX_PARTS) return OR_EINVAL;
 

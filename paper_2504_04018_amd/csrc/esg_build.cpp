@@ -1,11 +1,14 @@
 // Host builder of the HBI-2D elastic-graph index (Section 4.2, Alg. 3).
 //
-// The segment tree over positions [0, n-1] splits node [a,b] at
-// floor((a+b)/2).  A node with b - a >= leaf owns a proximity graph; its
-// graph is a copy of its left child's graph plus the insertion of the
-// right half (Alg. 3); when the left child is a leaf its graph is first
-// built from scratch.  Every graph of one tree depth covers disjoint
-// positions, so the graphs of depth t share one adjacency array adj[t][n][R].
+// The segment tree over positions [0, n-1] splits node [a,b] of L points
+// into `fanout` children, child j = [a + ceil(jL/f), a + ceil((j+1)L/f) - 1]
+// (at fanout 2: [a, floor((a+b)/2)] and the rest, as in Alg. 3; larger
+// fanouts are the extension of Section 4.2).  A node with b - a >= leaf owns
+// a proximity graph; its graph is a copy of its first child's graph plus
+// the insertion of the remaining points (Alg. 3); when the first child is a
+// leaf its graph is first built from scratch.  Every graph of one tree
+// depth covers disjoint positions, so the graphs of depth t share one
+// adjacency array adj[t][n][R].
 //
 // Insertion follows the graph-index construction recalled in Section 2.1:
 // a beam search of width ef_construction finds candidates, edge occlusion
@@ -71,9 +74,12 @@ struct VisitTags {
   }
 };
 
+// First position of child j of the node starting at a with L points.
+inline int64_t child_start(int64_t a, int64_t L, int f, int64_t j) { return a + (j * L + f - 1) / f; }
+
 struct Builder {
   int64_t n;
-  int d, R, leaf, efc, batch_max, n_depth, verbose;
+  int d, R, leaf, efc, batch_max, n_depth, verbose, fanout;
   const float* X;          // [n][d], position order
   uint32_t* adj;           // [n_depth][n][R]
 
@@ -233,11 +239,78 @@ struct Builder {
     }
   }
 
+  // Connectivity repair of the graph of node [a,b] at depth t: every point
+  // must be reachable from the entry e, so that a search with a beam as large
+  // as the node visits all of it (Finding 1: the superset graph then answers
+  // the sub-range exactly).  Occlusion pruning of reverse edges can leave a
+  // point without in-edges.  Each round walks the graph from e and gives
+  // every unreachable point u (in position order) an in-edge from a
+  // reachable point v: the nearest reachable point with a free row slot
+  // among u's neighbours and their neighbours, else u's nearest reachable
+  // neighbour (its last slot is overwritten; a later round repairs whatever
+  // that cuts off), else the nearest reachable point of the node with a free
+  // slot.  Sequential and in a fixed order, so the result is deterministic.
+  // Returns the number of edges added.
+  int64_t repair(int t, int64_t a, int64_t b, uint32_t e) {
+    uint32_t* rw = rows(t);
+    const int64_t L = b - a + 1;
+    std::vector<uint8_t> reach((size_t)L);
+    std::vector<uint32_t> queue;
+    int64_t added = 0;
+    for (int round = 0; round < 64; round++) {
+      std::fill(reach.begin(), reach.end(), 0);
+      queue.clear();
+      queue.push_back(e);
+      reach[(size_t)(e - a)] = 1;
+      for (size_t i = 0; i < queue.size(); i++) {
+        const uint32_t* row = rw + (size_t)queue[i] * R;
+        for (int s = 0; s < R && row[s] != ESG_NO_NODE; s++)
+          if (!reach[(size_t)(row[s] - a)]) {
+            reach[(size_t)(row[s] - a)] = 1;
+            queue.push_back(row[s]);
+          }
+      }
+      if ((int64_t)queue.size() == L) break;
+      const bool last_resort = round >= 48;
+      for (int64_t u = a; u <= b; u++) {
+        if (reach[(size_t)(u - a)]) continue;
+        const float* xu = vec((uint32_t)u);
+        uint32_t best = ESG_NO_NODE, near = ESG_NO_NODE;
+        float bd = INFINITY, nd = INFINITY;
+        auto consider = [&](uint32_t v) {
+          if (v == ESG_NO_NODE || !reach[(size_t)(v - a)]) return;
+          const float dv = l2sq(xu, vec(v), d);
+          if (dv < nd || (dv == nd && v < near)) { nd = dv; near = v; }
+          if (row_len(rw + (size_t)v * R, R) < R && (dv < bd || (dv == bd && v < best))) {
+            bd = dv;
+            best = v;
+          }
+        };
+        const uint32_t* ru = rw + (size_t)u * R;
+        for (int s = 0; s < R && ru[s] != ESG_NO_NODE; s++) {
+          consider(ru[s]);
+          const uint32_t* r2 = rw + (size_t)ru[s] * R;
+          for (int s2 = 0; s2 < R && r2[s2] != ESG_NO_NODE; s2++) consider(r2[s2]);
+        }
+        if (best == ESG_NO_NODE && (near == ESG_NO_NODE || last_resort)) {
+          for (int64_t v = a; v <= b; v++) consider((uint32_t)v);
+        }
+        uint32_t v = best != ESG_NO_NODE ? best : near;
+        if (v == ESG_NO_NODE) continue;
+        uint32_t* rv = rw + (size_t)v * R;
+        const int len = row_len(rv, R);
+        rv[len < R ? len : R - 1] = (uint32_t)u;
+        added++;
+      }
+    }
+    return added;
+  }
+
   void build_node(int t, int64_t a, int64_t b, bool par) {
-    int64_t mid = (a + b) / 2;
+    const int64_t mid = child_start(a, b - a + 1, fanout, 1) - 1;   // end of the first child
     uint32_t* rw = rows(t);
     if (mid - a >= leaf) {
-      // left child owns a graph at depth t+1: copy it
+      // first child owns a graph at depth t+1: copy it
       std::memcpy(rw + (size_t)a * R, rows(t + 1) + (size_t)a * R,
                   sizeof(uint32_t) * (size_t)R * (size_t)(mid - a + 1));
     } else {
@@ -254,12 +327,14 @@ struct NodeRef {
   int64_t heap, a, b;
 };
 
-void collect(int64_t a, int64_t b, int depth, int64_t heap, int leaf, std::vector<NodeRef>& out) {
+void collect(int64_t a, int64_t b, int depth, int64_t heap, int leaf, int f,
+             std::vector<NodeRef>& out) {
   if (b - a < leaf) return;
   out.push_back({depth, heap, a, b});
-  int64_t mid = (a + b) / 2;
-  collect(a, mid, depth + 1, 2 * heap, leaf, out);
-  collect(mid + 1, b, depth + 1, 2 * heap + 1, leaf, out);
+  for (int64_t j = 0; j < f; j++) {
+    const int64_t ca = child_start(a, b - a + 1, f, j), cb = child_start(a, b - a + 1, f, j + 1) - 1;
+    if (ca <= cb) collect(ca, cb, depth + 1, (int64_t)f * (heap - 1) + 2 + j, leaf, f, out);
+  }
 }
 
 bool write_all(FILE* f, const void* p, uint64_t bytes) {
@@ -294,8 +369,10 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
     return ESG_EINVAL;
   const esg_build_params& P = *params;
   if (P.degree < 1 || P.degree > ESG_DEGREE_MAX || P.leaf < 1 || P.ef_construction < 1 ||
-      (P.fanout != 2 && P.fanout != 0))
-    return P.fanout != 2 && P.fanout != 0 ? ESG_EUNSUPPORTED : ESG_EINVAL;
+      P.fanout < 0 || P.fanout == 1)
+    return ESG_EINVAL;
+  const int fanout = P.fanout == 0 ? 2 : P.fanout;
+  if (fanout > ESG_FANOUT_MAX) return ESG_EUNSUPPORTED;
   for (int64_t i = 0; i < n; i++)
     if (std::isnan(attr[i])) return ESG_EINVAL;
   try {
@@ -316,10 +393,10 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
     }
 
     std::vector<NodeRef> nodes;
-    collect(0, n - 1, 0, 1, P.leaf, nodes);
+    collect(0, n - 1, 0, 1, P.leaf, fanout, nodes);
     int n_depth = 0;
     for (const NodeRef& nd : nodes) n_depth = std::max(n_depth, nd.depth + 1);
-    if (n_depth > 40) return ESG_ERANGE;
+    if (n_depth > 40 || esg::ep_count(n_depth, fanout) == 0) return ESG_ERANGE;
 
     Builder B;
     B.n = n;
@@ -330,11 +407,12 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
     B.batch_max = P.batch_max > 0 ? P.batch_max : 1024;
     B.n_depth = n_depth;
     B.verbose = P.verbose;
+    B.fanout = fanout;
     B.X = X.data();
     std::vector<uint32_t> adj((size_t)n_depth * (size_t)n * (size_t)P.degree, ESG_NO_NODE);
     B.adj = adj.data();
 
-    std::vector<uint32_t> ep((size_t)1 << n_depth, ESG_NO_NODE);
+    std::vector<uint32_t> ep((size_t)esg::ep_count(n_depth, fanout), ESG_NO_NODE);
     for (int t = n_depth - 1; t >= 0; t--) {
       std::vector<NodeRef> level;
       for (const NodeRef& nd : nodes)
@@ -347,10 +425,17 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
       } else {
         for (const NodeRef& nd : level) B.build_node(t, nd.a, nd.b, true);
       }
-#pragma omp parallel for schedule(dynamic, 1)
-      for (int64_t i = 0; i < (int64_t)level.size(); i++)
-        ep[(size_t)level[(size_t)i].heap] = B.medoid(level[(size_t)i].a, level[(size_t)i].b);
-      if (P.verbose) fprintf(stderr, "[esg_build] depth %d: %zu graph nodes\n", t, level.size());
+      int64_t repaired = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : repaired)
+      for (int64_t i = 0; i < (int64_t)level.size(); i++) {
+        const NodeRef& nd = level[(size_t)i];
+        const uint32_t e = B.medoid(nd.a, nd.b);
+        ep[(size_t)nd.heap] = e;
+        repaired += B.repair(t, nd.a, nd.b, e);
+      }
+      if (P.verbose)
+        fprintf(stderr, "[esg_build] depth %d: %zu graph nodes, %lld edges added for reachability\n",
+                t, level.size(), (long long)repaired);
     }
 
     // Write the file.
@@ -363,22 +448,22 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
     h.d = d;
     h.degree = P.degree;
     h.leaf = P.leaf;
-    h.fanout = 2;
+    h.fanout = fanout;
     h.n_depth = n_depth;
-    h.c_den = 2;
+    h.c_den = fanout;   // elastic constant c = 1/fanout (Lemma 4.3)
     h.ef_construction = P.ef_construction;
     h.off_ids = esg::align_up(esg::kHeaderBytes);
     h.off_attr = esg::align_up(h.off_ids + esg::bytes_ids(n));
     h.off_vec = esg::align_up(h.off_attr + esg::bytes_attr(n));
     h.off_adj = esg::align_up(h.off_vec + esg::bytes_vec(n, d));
     h.off_ep = esg::align_up(h.off_adj + esg::bytes_adj(n, n_depth, P.degree));
-    h.file_bytes = h.off_ep + esg::bytes_ep(n_depth);
+    h.file_bytes = h.off_ep + esg::bytes_ep(n_depth, fanout);
     const esg::Crc32c& crc = esg::crc32c();
     h.crc_sections[0] = crc.update(0, order.data(), esg::bytes_ids(n));
     h.crc_sections[1] = crc.update(0, sorted_attr.data(), esg::bytes_attr(n));
     h.crc_sections[2] = crc.update(0, X.data(), esg::bytes_vec(n, d));
     h.crc_sections[3] = crc.update(0, adj.data(), esg::bytes_adj(n, n_depth, P.degree));
-    h.crc_sections[4] = crc.update(0, ep.data(), esg::bytes_ep(n_depth));
+    h.crc_sections[4] = crc.update(0, ep.data(), esg::bytes_ep(n_depth, fanout));
     h.crc_header = crc.update(0, &h, offsetof(esg::FileHeader, crc_header));
 
     FILE* f = fopen(out_path, "wb");
@@ -388,7 +473,7 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
               write_all(f, sorted_attr.data(), esg::bytes_attr(n)) && pad_to(f, h.off_vec) &&
               write_all(f, X.data(), esg::bytes_vec(n, d)) && pad_to(f, h.off_adj) &&
               write_all(f, adj.data(), esg::bytes_adj(n, n_depth, P.degree)) &&
-              pad_to(f, h.off_ep) && write_all(f, ep.data(), esg::bytes_ep(n_depth));
+              pad_to(f, h.off_ep) && write_all(f, ep.data(), esg::bytes_ep(n_depth, fanout));
     ok = (fclose(f) == 0) && ok;
     return ok ? ESG_OK : ESG_EIO;
   } catch (const std::bad_alloc&) {

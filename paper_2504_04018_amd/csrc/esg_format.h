@@ -37,7 +37,21 @@ inline uint64_t bytes_vec(int64_t n, int32_t d) { return (uint64_t)n * (uint64_t
 inline uint64_t bytes_adj(int64_t n, int32_t depth, int32_t r) {
   return (uint64_t)depth * (uint64_t)n * (uint64_t)r * 4;
 }
-inline uint64_t bytes_ep(int32_t depth) { return ((uint64_t)1 << depth) * 4; }
+// Entry-point table: tree nodes are numbered breadth-first from the root 1
+// (child j of node h is fanout*(h-1) + 2 + j), so the nodes of depths
+// 0..depth-1 take the numbers 1 .. sum of fanout^t; slot 0 is unused.
+// Returns 0 when the count would exceed 2^32.
+inline uint64_t ep_count(int32_t depth, int32_t fanout) {
+  uint64_t c = 1, level = 1;
+  for (int32_t t = 0; t < depth; t++) {
+    c += level;
+    if (c > (1ull << 32)) return 0;
+    level *= (uint64_t)fanout;
+    if (level > (1ull << 32)) level = (1ull << 33);
+  }
+  return c;
+}
+inline uint64_t bytes_ep(int32_t depth, int32_t fanout) { return ep_count(depth, fanout) * 4; }
 
 // Software CRC-32C (Castagnoli, reflected polynomial 0x82F63B78), eight
 // bytes per step with slicing tables.

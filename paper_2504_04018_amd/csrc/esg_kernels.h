@@ -41,6 +41,8 @@ struct SearchArgs {
   const int64_t* ext_id;  // [n]
   int64_t n;
   int32_t d, dp, R, leaf, n_depth, c_den;
+  int32_t fanout;         // children per tree node
+  int32_t pad0_;
   // batch
   const float* queries;   // [nq][d]
   const int64_t* l;
@@ -56,7 +58,8 @@ struct SearchArgs {
   int64_t visited_cap;
   int64_t* n_invalid;
   // workspace
-  uint32_t* spill;        // [slots][spill_words] visited bitmaps used after the LDS hash fills
+  uint32_t* spill;        // [slots][spill_words + spill log] visited bitmaps (all zero
+                          // between parts) used after the LDS hash fills, and their logs
   int64_t spill_words;
   int64_t spill_slots;
   uint32_t* counter;      // work-queue head

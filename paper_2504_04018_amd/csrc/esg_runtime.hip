@@ -59,7 +59,7 @@ hipError_t dev_alloc(void** p, size_t bytes) {
 struct esg_index {
   int device = 0;
   int64_t n = 0;
-  int32_t d = 0, dp = 0, R = 0, leaf = 0, n_depth = 0, c_den = 2;
+  int32_t d = 0, dp = 0, R = 0, leaf = 0, n_depth = 0, c_den = 2, fanout = 2;
   float* vec = nullptr;
   uint16_t* vec16 = nullptr;
   uint8_t* vec8 = nullptr;
@@ -291,8 +291,8 @@ bool read_exact(FILE* f, uint64_t off, void* dst, uint64_t bytes) {
   return true;
 }
 
-bool tree_is_consistent(int64_t n, int32_t leaf, int32_t n_depth, int32_t R, const uint32_t* adj,
-                        const uint32_t* ep) {
+bool tree_is_consistent(int64_t n, int32_t leaf, int32_t fanout, int32_t n_depth, int32_t R,
+                        const uint32_t* adj, const uint32_t* ep) {
   struct Node {
     int64_t a, b, heap;
     int32_t depth;
@@ -311,9 +311,12 @@ bool tree_is_consistent(int64_t n, int32_t leaf, int32_t n_depth, int32_t R, con
         const uint32_t v = rows[(size_t)p * R + j];
         if (v != ESG_NO_NODE && ((int64_t)v < nd.a || (int64_t)v > nd.b)) return false;
       }
-    const int64_t mid = (nd.a + nd.b) / 2;
-    todo.push_back({nd.a, mid, 2 * nd.heap, nd.depth + 1});
-    todo.push_back({mid + 1, nd.b, 2 * nd.heap + 1, nd.depth + 1});
+    const int64_t L = nd.b - nd.a + 1;
+    for (int64_t j = 0; j < fanout; j++) {
+      const int64_t ca = nd.a + (j * L + fanout - 1) / fanout;
+      const int64_t cb = nd.a + ((j + 1) * L + fanout - 1) / fanout - 1;
+      if (ca <= cb) todo.push_back({ca, cb, (int64_t)fanout * (nd.heap - 1) + 2 + j, nd.depth + 1});
+    }
   }
   return true;
 }
@@ -342,11 +345,13 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
     return ESG_EFORMAT;
   if (crc.update(0, &h, offsetof(esg::FileHeader, crc_header)) != h.crc_header) return ESG_EFORMAT;
   if (h.n <= 0 || h.n >= (int64_t)ESG_NO_NODE || h.d <= 0 || h.d > 65536 || h.degree < 1 ||
-      h.degree > ESG_DEGREE_MAX || h.leaf < 1 || h.fanout != 2 || h.n_depth < 0 ||
-      h.n_depth > 40 || h.c_den < h.fanout)
+      h.degree > ESG_DEGREE_MAX || h.leaf < 1 || h.fanout < 2 || h.fanout > ESG_FANOUT_MAX ||
+      h.n_depth < 0 || h.n_depth > 40 || h.c_den < h.fanout ||
+      esg::ep_count(h.n_depth, h.fanout) == 0)
     return ESG_EFORMAT;   // c = 1/c_den <= 1/fanout keeps Alg. 4 at two parts at most
   const uint64_t sizes[5] = {esg::bytes_ids(h.n), esg::bytes_attr(h.n), esg::bytes_vec(h.n, h.d),
-                             esg::bytes_adj(h.n, h.n_depth, h.degree), esg::bytes_ep(h.n_depth)};
+                             esg::bytes_adj(h.n, h.n_depth, h.degree),
+                             esg::bytes_ep(h.n_depth, h.fanout)};
   const uint64_t offs[5] = {h.off_ids, h.off_attr, h.off_vec, h.off_adj, h.off_ep};
   uint64_t prev_end = esg::kHeaderBytes;
   for (int s = 0; s < 5; s++) {
@@ -366,7 +371,7 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
   std::vector<int64_t> ids((size_t)h.n);
   std::vector<float> vec((size_t)h.n * (size_t)h.d);
   std::vector<uint32_t> adj((size_t)h.n_depth * (size_t)h.n * (size_t)h.degree);
-  std::vector<uint32_t> ep((size_t)1 << h.n_depth);
+  std::vector<uint32_t> ep((size_t)esg::ep_count(h.n_depth, h.fanout));
   std::vector<double> attr((size_t)h.n);
   void* dsts[5] = {ids.data(), attr.data(), vec.data(), adj.data(), ep.data()};
   for (int s = 0; s < 5; s++) {
@@ -375,7 +380,7 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
   }
   // Structural checks the kernels rely on: every graph node [a,b] of the
   // tree has its entry point and all neighbours of its rows inside [a,b].
-  if (!tree_is_consistent(h.n, h.leaf, h.n_depth, h.degree, adj.data(), ep.data()))
+  if (!tree_is_consistent(h.n, h.leaf, h.fanout, h.n_depth, h.degree, adj.data(), ep.data()))
     return ESG_EFORMAT;
 
   int ndev = 0;
@@ -396,6 +401,7 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
   ix->leaf = h.leaf;
   ix->n_depth = h.n_depth;
   ix->c_den = h.c_den;
+  ix->fanout = h.fanout;
   ix->kt = kt;
   if (hipDeviceGetAttribute(&ix->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device) !=
       hipSuccess) {
@@ -413,7 +419,8 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
   A((void**)&ix->adj, std::max<size_t>(4, adj.size() * 4));
   A((void**)&ix->ep, ep.size() * 4);
   A((void**)&ix->ext_id, ids.size() * 8);
-  A((void**)&ix->spill, (size_t)ix->spill_slots * ix->spill_words * 4);
+  const size_t spill_bytes = (size_t)ix->spill_slots * (ix->spill_words + esgk::kSpillLog) * 4;
+  A((void**)&ix->spill, spill_bytes);
   A((void**)&ix->counter, 256);
   A((void**)&ix->mlp_pack, sizeof(float) * esgk::kMlpParams);
   if (st != ESG_OK) {
@@ -430,6 +437,7 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
             hipMemcpy(ix->ext_id, ids.data(), ids.size() * 8, hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemset(ix->counter, 0, 256) == hipSuccess &&
+            hipMemset(ix->spill, 0, spill_bytes) == hipSuccess &&   // bitmaps start all zero
             hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
@@ -489,7 +497,7 @@ int32_t esg_index_info(const esg_index* idx, esg_index_info_t* out) {
   out->d = idx->d;
   out->degree = idx->R;
   out->leaf = idx->leaf;
-  out->fanout = 2;
+  out->fanout = idx->fanout;
   out->n_depth = idx->n_depth;
   out->c_den = idx->c_den;
   out->has_bf16 = idx->vec16 != nullptr;
@@ -863,6 +871,7 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   a.leaf = idx->leaf;
   a.n_depth = idx->n_depth;
   a.c_den = idx->c_den;
+  a.fanout = idx->fanout;
   a.queries = queries;
   a.l = l;
   a.r = r;

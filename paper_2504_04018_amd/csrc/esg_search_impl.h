@@ -317,17 +317,25 @@ __device__ __forceinline__ void list_clear(uint64_t (&L)[E]) {
 // identify k.  A slot holds 0 (empty) or 0x8000 | j << 12 | low bits, where
 // j < 8 is the distance from the home slot (linear probing).  A key whose
 // 8 probe slots are all taken goes to a per-wave bitmap in global memory
-// over [a,b] (cleared on first use); a lookup that meets 8 taken slots
-// without a match consults the bitmap.  Slots are never freed, so both
-// structures stay exact.
+// over [a,b]; a lookup that meets 8 taken slots without a match consults
+// the bitmap.  Slots are never freed, so both structures stay exact.
+//
+// The bitmap is all zero between parts: each spilled key's word index is
+// appended to a per-wave log, and at the end of the part exactly those
+// words are cleared (the whole [a,b] span only if the log overflowed).  A
+// part that never spills writes nothing to global memory for its visited
+// set.
+
+constexpr int kSpillLog = 4096;   // logged bitmap words per wave slot
 
 struct Visited {
   uint32_t* table;   // T/2 words of two 16-bit slots
   uint32_t* bm;      // spill bitmap of this wave slot, indexed by position - a
+  uint32_t* log;     // [kSpillLog] bitmap words set during the current part
   uint32_t a, b;
   uint32_t kb_mask;  // 2^kb - 1
   int kb, shift;     // shift = kb - log2(T) (stored low bits)
-  bool spill;
+  int nlog;          // keys spilled in the current part (wave-uniform)
 };
 
 __device__ __forceinline__ uint32_t vkey_mix(uint32_t k, const Visited& V) {
@@ -335,12 +343,19 @@ __device__ __forceinline__ uint32_t vkey_mix(uint32_t k, const Visited& V) {
   return x ^ (x >> ((V.kb + 1) >> 1));
 }
 
-// Clears the bitmap over [a,b] the first time a key spills in this part.
-__device__ __forceinline__ void visited_spill_begin(Visited& V, int lane) {
-  const uint32_t words = ((V.b - V.a) >> 5) + 1u;
-  for (uint32_t i = (uint32_t)lane; i < words; i += kWave) V.bm[i] = 0u;
-  __threadfence();
-  V.spill = true;
+// End of a part: clears the bitmap words its spilled keys set, leaving the
+// bitmap all zero for the next part.
+__device__ __forceinline__ void visited_finish(Visited& V, int lane) {
+  if (V.nlog == 0) return;
+  __threadfence();   // every lane's log entries and bitmap updates are visible
+  if (V.nlog <= kSpillLog) {
+    for (int i = lane; i < V.nlog; i += kWave) V.bm[V.log[i]] = 0u;
+  } else {
+    const uint32_t words = ((V.b - V.a) >> 5) + 1u;
+    for (uint32_t i = (uint32_t)lane; i < words; i += kWave) V.bm[i] = 0u;
+  }
+  __threadfence();   // the clears land before the next part's updates
+  V.nlog = 0;
 }
 
 // Test-and-set of v for active lanes; true when v was not visited before.
@@ -377,12 +392,14 @@ __device__ __forceinline__ bool visit(const SearchArgs& A, Visited& V, uint32_t 
   }
   const uint64_t om = ballot(overflow);
   if (om != 0) {
-    if (!V.spill) visited_spill_begin(V, lane);
     if (overflow) {
       const uint32_t off = v - V.a;
       const uint32_t bit = 1u << (off & 31u);
       is_new = (atomicOr(&V.bm[off >> 5], bit) & bit) == 0u;
+      const int at = V.nlog + rank_below(om);
+      if (at < kSpillLog) V.log[at] = off >> 5;
     }
+    V.nlog += __popcll(om);
   }
   return is_new;
 }
@@ -397,7 +414,7 @@ __device__ __forceinline__ void visited_reset(const SearchArgs& A, Visited& V, u
   V.kb = kb;
   V.kb_mask = kb >= 32 ? 0xFFFFFFFFu : ((1u << kb) - 1u);
   V.shift = kb - tbits;
-  V.spill = false;
+  V.nlog = 0;
   uint4* t4 = reinterpret_cast<uint4*>(V.table);
   for (int i = lane; i < A.hash_cap / 8; i += kWave) t4[i] = make_uint4(0, 0, 0, 0);
   wave_lds_sync();
@@ -414,31 +431,45 @@ struct Part {
 
 // One descent of Alg. 4 from node (a,b) with part (x,y): follows the single
 // child that holds the part until a leaf or an elastic node is reached, or
-// (when allow_split) until the part straddles a split point, in which case
-// the two halves are returned in `left`/`right` and false is returned.
+// (when allow_split) until the part straddles two children, in which case
+// the two pieces are returned in `it`/`right` with split = true.  Node
+// [a,b] of L points has `fanout` children, child j starting at
+// a + ceil(jL/fanout), so position p lies in child floor(fanout (p-a) / L);
+// child j of node h is numbered fanout (h-1) + 2 + j.  A part that is not
+// elastic at c = 1/fanout never straddles three children (the middle one
+// would hold >= L/fanout of its points: Lemma 4.3); false is returned if it
+// does, or if a piece of a split would straddle again.
 struct Desc {
   int64_t a, b, x, y, heap;
   int32_t depth;
 };
 
-__device__ __forceinline__ bool descend(Desc& it, int64_t leaf, int32_t c_den, bool allow_split,
-                                        Desc& right, bool& split) {
+__device__ __forceinline__ int64_t child_begin(int64_t a, int64_t L, int32_t f, int64_t j) {
+  return a + (j * L + f - 1) / f;
+}
+
+__device__ __forceinline__ bool descend(Desc& it, int64_t leaf, int32_t c_den, int32_t fanout,
+                                        bool allow_split, Desc& right, bool& split) {
   split = false;
   for (int guard = 0; guard < 64; guard++) {
+    const int64_t L = it.b - it.a + 1;
     const bool is_leaf = it.b - it.a < leaf;
-    const bool elastic = !is_leaf && (int64_t)c_den * (it.y - it.x + 1) >= (it.b - it.a + 1);
+    const bool elastic = !is_leaf && (int64_t)c_den * (it.y - it.x + 1) >= L;
     if (is_leaf || elastic) return true;
-    const int64_t mid = (it.a + it.b) / 2;
-    const bool go_left = it.x <= mid, go_right = it.y > mid;
-    if (go_left && go_right) {
-      if (!allow_split) return false;
-      right = {mid + 1, it.b, mid + 1, it.y, 2 * it.heap + 1, it.depth + 1};
-      it = {it.a, mid, it.x, mid, 2 * it.heap, it.depth + 1};
-      split = true;
-      return true;
+    const int64_t jx = (int64_t)fanout * (it.x - it.a) / L;
+    const int64_t jy = (int64_t)fanout * (it.y - it.a) / L;
+    const int64_t h0 = (int64_t)fanout * (it.heap - 1) + 2;
+    const int64_t s0 = child_begin(it.a, L, fanout, jx), s1 = child_begin(it.a, L, fanout, jx + 1);
+    if (jy == jx) {
+      it = {s0, s1 - 1, it.x, it.y, h0 + jx, it.depth + 1};
+      continue;
     }
-    if (go_left) it = {it.a, mid, it.x, it.y, 2 * it.heap, it.depth + 1};
-    else it = {mid + 1, it.b, it.x, it.y, 2 * it.heap + 1, it.depth + 1};
+    if (jy != jx + 1 || !allow_split) return false;
+    const int64_t s2 = child_begin(it.a, L, fanout, jx + 2);
+    right = {s1, s2 - 1, s1, it.y, h0 + jx + 1, it.depth + 1};
+    it = {s0, s1 - 1, it.x, s1 - 1, h0 + jx, it.depth + 1};
+    split = true;
+    return true;
   }
   return false;
 }
@@ -448,21 +479,22 @@ __device__ __forceinline__ Part to_part(const Desc& it, int64_t leaf) {
           (uint32_t)it.x, (uint32_t)it.y};
 }
 
-// Alg. 4: at most two parts for fanout 2 (Lemma 4.2).  Returns the count
-// (or -1 if the descent would emit more: never for a fanout-2 tree) and part
-// `which` (0 or 1) in `out`.  The search recomputes the descent for each part
-// (a few scalar steps) so that no part record has to be kept in memory.
-__device__ __forceinline__ int select_parts(int64_t n, int64_t leaf, int32_t c_den, int64_t lq,
-                                            int64_t rq, int which, Part& out) {
+// Alg. 4: at most two parts (Lemma 4.2 at fanout 2, Lemma 4.3 at fanout f
+// with c = 1/f).  Returns the count (or -1 if the descent would emit more:
+// never when c_den >= fanout, which the loader enforces) and part `which`
+// (0 or 1) in `out`.  The search recomputes the descent for each part (a few
+// scalar steps) so that no part record has to be kept in memory.
+__device__ __forceinline__ int select_parts(int64_t n, int64_t leaf, int32_t c_den, int32_t fanout,
+                                            int64_t lq, int64_t rq, int which, Part& out) {
   Desc it = {0, n - 1, lq, rq, 1, 0}, right = it, dummy = it;
   bool split = false, s2 = false;
-  if (!descend(it, leaf, c_den, true, right, split)) return -1;
+  if (!descend(it, leaf, c_den, fanout, true, right, split)) return -1;
   if (!split) {
     out = to_part(it, leaf);
     return 1;
   }
-  if (!descend(it, leaf, c_den, false, dummy, s2)) return -1;
-  if (!descend(right, leaf, c_den, false, dummy, s2)) return -1;
+  if (!descend(it, leaf, c_den, fanout, false, dummy, s2)) return -1;
+  if (!descend(right, leaf, c_den, fanout, false, dummy, s2)) return -1;
   if (which == 1) it = right;
   out = to_part(it, leaf);
   return 2;

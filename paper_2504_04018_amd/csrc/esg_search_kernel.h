@@ -305,6 +305,7 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
   if (go)
     while (hop(false)) {
     }
+  visited_finish(V, lane);
   return {hops, nvis};
 }
 
@@ -368,7 +369,7 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
   const int64_t lq = A.l[qi], rq = A.r[qi];
   const bool valid = lq >= 0 && rq < A.n && lq <= rq;
   Part pt{};
-  const int np = valid ? select_parts(A.n, A.leaf, A.c_den, lq, rq, 0, pt) : 0;
+  const int np = valid ? select_parts(A.n, A.leaf, A.c_den, A.fanout, lq, rq, 0, pt) : 0;
   if (!valid || np < 0) {
     for (int i = lane; i < k; i += kWave) {
       ids[i] = -1;
@@ -390,7 +391,7 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
   // One copy of the part code (not unrolled: half the instruction footprint).
 #pragma nounroll
   for (int p = 0; p < np; p++) {
-    if (p == 1) select_parts(A.n, A.leaf, A.c_den, lq, rq, 1, pt);
+    if (p == 1) select_parts(A.n, A.leaf, A.c_den, A.fanout, lq, rq, 1, pt);
     uint64_t Qp[E];
     PartStats st{0, 0};
     const uint64_t t_start = A.trace ? __builtin_amdgcn_s_memrealtime() : 0;
@@ -465,11 +466,12 @@ void search_kernel(SearchArgs A) {
   const int64_t slot = (int64_t)blockIdx.x * kWavesPerGroup + wid;
   Visited V;
   V.table = wave_table(Ls);
-  V.bm = A.spill + slot * A.spill_words;
+  V.bm = A.spill + slot * (A.spill_words + kSpillLog);
+  V.log = V.bm + A.spill_words;
   V.a = V.b = 0;
   V.kb = V.shift = 0;
   V.kb_mask = 0;
-  V.spill = false;
+  V.nlog = 0;
   const int64_t count = A.qcount ? (int64_t)*A.qcount : A.nq;
   for (;;) {
     uint32_t t = 0;

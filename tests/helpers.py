@@ -13,8 +13,12 @@ import oracle
 NO = 0xFFFFFFFF
 
 
-def tree_nodes(n: int, leaf: int):
-    """All tree nodes as (depth, heap, a, b, is_graph), breadth-first."""
+def tree_nodes(n: int, leaf: int, fanout: int = 2):
+    """All tree nodes as (depth, heap, a, b, is_graph), breadth-first.  Node
+    [a,b] of L points splits into fanout children of L/fanout points each,
+    rounded so that child j starts at a + ceil(j L / fanout) (at fanout 2:
+    [a, floor((a+b)/2)] and the rest); child j of node h is numbered
+    fanout (h - 1) + 2 + j."""
     out = []
     todo = [(0, 1, 0, n - 1)]
     while todo:
@@ -23,9 +27,12 @@ def tree_nodes(n: int, leaf: int):
             g = (b - a) >= leaf
             out.append((depth, heap, a, b, g))
             if g and a < b:
-                m = (a + b) // 2
-                nxt.append((depth + 1, 2 * heap, a, m))
-                nxt.append((depth + 1, 2 * heap + 1, m + 1, b))
+                L = b - a + 1
+                starts = [a + -(-j * L // fanout) for j in range(fanout + 1)]
+                for j in range(fanout):
+                    if starts[j] <= starts[j + 1] - 1:
+                        nxt.append((depth + 1, fanout * (heap - 1) + 2 + j, starts[j],
+                                    starts[j + 1] - 1))
         todo = nxt
     return out
 

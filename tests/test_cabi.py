@@ -44,17 +44,29 @@ def small_index(tmp_path_factory):
     return w, path
 
 
-def test_builder_structure(small_index):
-    """Alg. 3 output: one graph per tree node with b-a >= leaf, neighbours
-    inside the node, no self loops or repeats, degree <= R, rows packed,
-    entry point inside the node, position order = attribute order."""
-    w, path = small_index
+@pytest.fixture(scope="module", params=[2, 4, 16])
+def fanout_index(request, tmp_path_factory):
+    f = request.param
+    w = synth.make_workload(0, n=3000, nq=0)
+    path = str(tmp_path_factory.mktemp(f"cabi_f{f}") / "s.esgi")
+    esg.build_index(w["X"], w["attr"].astype(np.float64), path, degree=12, leaf=100,
+                    ef_construction=64, fanout=f)
+    return w, path, f
+
+
+def test_builder_structure(fanout_index):
+    """Alg. 3 output on a fanout-f tree (f = 2, 4, 16; Section 4.2,
+    Extensions): one graph per tree node with b-a >= leaf, neighbours inside
+    the node, no self loops or repeats, degree <= R, rows packed, entry point
+    inside the node, position order = attribute order, c = 1/f."""
+    w, path, f = fanout_index
     ix = oracle.read_index(path)
+    assert ix.fanout == f and ix.c_den == f
     assert np.array_equal(np.sort(w["attr"]), ix.attr)
     assert np.array_equal(ix.vec, w["X"][ix.ext_id])
     from tests.helpers import tree_nodes
     depth_seen = set()
-    for t, h, a, b, g in tree_nodes(ix.n, ix.leaf):
+    for t, h, a, b, g in tree_nodes(ix.n, ix.leaf, f):
         if not g:
             continue
         depth_seen.add(t)
@@ -71,6 +83,47 @@ def test_builder_structure(small_index):
             assert len(set(rv.tolist())) == len(rv) and (a + i) not in rv.tolist()
         assert valid.sum(1).min() >= 1
     assert depth_seen == set(range(ix.n_depth))
+    # rows of positions outside every graph node of a depth stay empty
+    for t in range(ix.n_depth):
+        covered = np.zeros(ix.n, bool)
+        for tt, h, a, b, g in tree_nodes(ix.n, ix.leaf, f):
+            if tt == t and g:
+                covered[a:b + 1] = True
+        assert np.all(ix.adj[t][~covered] == oracle.NO_NODE)
+    # the tree is shallower at a larger fanout: 3000 points, leaf 100
+    assert ix.n_depth == {2: 5, 4: 3, 16: 2}[f]
+
+
+def test_fanout_index_oracle_invariants(fanout_index):
+    """The oracle's search on a fanout-f index: at most two parts per query
+    (Lemma 4.3), every answer inside [l,r], and an exhaustive beam
+    (ef >= every node size) equals the float64 brute force (Finding 1)."""
+    w, path, f = fanout_index
+    ix = oracle.read_index(path)
+    rng = np.random.default_rng(f)
+    Q = synth.make_workload(0, n=3000, nq=40)["Q"]
+    wd = np.rint(np.exp(rng.uniform(0, np.log(3000), 40))).astype(np.int64)
+    l = (rng.random(40) * (3000 - wd + 1)).astype(np.int64)
+    r = l + wd - 1
+    ids, dists, st, stats = oracle.query_batch(ix, Q, l, r, 10, 4096, 4096, with_stats=True)
+    assert np.all(st == 0) and np.all(stats[:, 0] <= 2)
+    pos_of = np.empty(ix.n, np.int64)
+    pos_of[ix.ext_id] = np.arange(ix.n)
+    pos = np.where(ids >= 0, pos_of[np.maximum(ids, 0)], -1)
+    assert np.all((pos == -1) | ((pos >= l[:, None]) & (pos <= r[:, None])))
+    gt_pos, gt_d = oracle.bruteforce(ix.vec, Q, l, r, 10)
+    rec, _, _ = oracle.recall(ix.vec, Q, l, r, pos, gt_pos, gt_d, 10)
+    assert rec == 1.0
+
+
+def test_builder_fanout_errors(tmp_path):
+    X = np.zeros((10, 4), np.float32)
+    with pytest.raises(esg.EsgError) as e:
+        esg.build_index(X, np.arange(10.0), str(tmp_path / "x"), fanout=1)
+    assert e.value.status == esg.ESG_EINVAL
+    with pytest.raises(esg.EsgError) as e:
+        esg.build_index(X, np.arange(10.0), str(tmp_path / "x"), fanout=65)
+    assert e.value.status == esg.ESG_EUNSUPPORTED
 
 
 def test_builder_deterministic(small_index, tmp_path):

@@ -88,7 +88,7 @@ def gpu_search(gix, Q, l, r, k, ef, visited_cap=0, **kw):
 
 
 def oracle_parts(oix, q, l, r, ef, cap_p, hop_budget=-1, kind=oracle.DIST_F32):
-    parts, cnt = oracle.select(oix.n, oix.leaf, l, r)
+    parts, cnt = oix.select(l, r)
     res = []
     for p in parts:
         if p["kind"] == oracle.KIND_GRAPH:

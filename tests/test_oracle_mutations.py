@@ -38,9 +38,10 @@ MUTATIONS = {
     # switch taken although the search stops right at the end of the probe
     "switch_when_stopping": ("h == sw->switch_hop &&\n        !(Q.len >= m && cand_less(Q.a[Q.len - 1], P.a[0]))) {",
                              "h == sw->switch_hop) {"),
-    # split point rounded up
-    "mid_rounded_up": ("int64_t mid = (a + b) / 2; /* a,b >= 0, so this is floor */",
-                       "int64_t mid = (a + b + 1) / 2;"),
+    # child boundaries rounded down (at fanout 2: the split point moves left)
+    "child_start_floor": ("return a + (j * L + f - 1) / f;", "return a + (j * L) / f;"),
+    # child numbering off by one
+    "child_heap": ("(int64_t)s->fanout * (heap - 1) + 2 + j,", "(int64_t)s->fanout * (heap - 1) + 1 + j,"),
     # strict elastic comparison
     "elastic_strict": ("return (int64_t)c_den * (y - x + 1) >= (b - a + 1);",
                        "return (int64_t)c_den * (y - x + 1) > (b - a + 1);"),

@@ -48,19 +48,40 @@ def test_selector_golden_cases():
     assert n_cases >= 10
 
 
-@pytest.mark.parametrize("n,leaf", [(1, 1), (2, 1), (7, 1), (16, 1), (33, 2), (50, 3), (64, 5),
-                                    (89, 1), (100, 16), (128, 4)])
-def test_selector_enumeration(n, leaf):
-    """Every range [l,r]: at most two parts (Lemma 4.2); the parts tile the
-    range left to right; each part lies in a tree node of the fanout-2
-    segment tree; graph parts hold at least half of their node (Def. 3.1,
-    c = 1/2) and sit on nodes that own a graph (Alg. 3); scans sit on leaves;
-    a split query becomes a suffix of one node and a prefix of another
-    (two half-bounded queries, Section 4.2 fanout discussion)."""
-    nodes = {(h): (t, a, b, g) for t, h, a, b, g in tree_nodes(n, leaf)}
+def test_selector_fanout_golden_cases():
+    """Alg. 4 on fanout-4 trees with c = 1/4 (Section 4.2, Extensions),
+    worked by hand (tests/golden/selector_cases_fanout.txt)."""
+    n_cases = 0
+    for line in open(os.path.join(GOLD, "selector_cases_fanout.txt")):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        lhs, rhs = line.split("|")
+        n, leaf, f, l, r = map(int, lhs.split())
+        parts, cnt = oracle.select(n, leaf, l, r, c_den=f, fanout=f)
+        assert cnt == len(parts)
+        assert parts == _parse_parts(rhs), (n, leaf, f, l, r, parts)
+        n_cases += 1
+    assert n_cases >= 14
+
+
+@pytest.mark.parametrize("n,leaf,f", [(1, 1, 2), (2, 1, 2), (7, 1, 2), (16, 1, 2), (33, 2, 2),
+                                      (50, 3, 2), (64, 5, 2), (89, 1, 2), (100, 16, 2),
+                                      (128, 4, 2), (60, 1, 3), (90, 2, 3), (64, 1, 4),
+                                      (100, 1, 4), (77, 3, 4), (130, 1, 8), (99, 2, 8),
+                                      (200, 1, 16), (150, 3, 16)])
+def test_selector_enumeration(n, leaf, f):
+    """Every range [l,r]: at most two parts (Lemma 4.2 at fanout 2, Lemma 4.3
+    at fanout f with c = 1/f); the parts tile the range left to right; each
+    part lies in a tree node of the fanout-f segment tree; graph parts hold
+    at least 1/f of their node (Def. 3.1) and sit on nodes that own a graph
+    (Alg. 3); scans sit on leaves; a split query becomes a suffix of one
+    node and a prefix of another (two half-bounded queries, Section 4.2,
+    Extensions)."""
+    nodes = {(h): (t, a, b, g) for t, h, a, b, g in tree_nodes(n, leaf, f)}
     for l in range(n):
         for r in range(l, n):
-            parts, cnt = oracle.select(n, leaf, l, r)
+            parts, cnt = oracle.select(n, leaf, l, r, c_den=f, fanout=f)
             assert 1 <= cnt <= 2
             cur = l
             for p in parts:
@@ -70,7 +91,7 @@ def test_selector_enumeration(n, leaf):
                 assert p["x"] == cur
                 cur = p["y"] + 1
                 if p["kind"] == oracle.KIND_GRAPH:
-                    assert g and 2 * (p["y"] - p["x"] + 1) >= b - a + 1
+                    assert g and f * (p["y"] - p["x"] + 1) >= b - a + 1
                 else:
                     assert b - a < leaf
             assert cur == r + 1
@@ -78,25 +99,37 @@ def test_selector_enumeration(n, leaf):
                 assert parts[0]["y"] == parts[0]["b"] and parts[1]["x"] == parts[1]["a"]
 
 
-@pytest.mark.parametrize("n,leaf", [(50, 1), (100, 3), (1000, 16), (4096, 64)])
-def test_selector_half_bounded_one_part(n, leaf):
+def test_fanout_lemma_needs_c_at_most_one_over_f():
+    """Lemma 4.3 ties the elastic constant to the fanout: with c = 1/2 on a
+    fanout-4 tree (a stricter test than 1/4), some ranges need more than
+    two parts -- so the two-part bound is the lemma's, not an accident."""
+    worst = 0
+    for l in range(64):
+        for r in range(l, 64):
+            worst = max(worst, oracle.select(64, 1, l, r, c_den=2, fanout=4)[1])
+    assert worst > 2
+
+
+@pytest.mark.parametrize("n,leaf,f", [(50, 1, 2), (100, 3, 2), (1000, 16, 2), (4096, 64, 2),
+                                      (100, 1, 4), (1000, 16, 8), (4096, 64, 16)])
+def test_selector_half_bounded_one_part(n, leaf, f):
     """Lemma 4.1: a prefix [0,r] (or suffix) is answered by one recorded
-    range holding it with ratio >= 1/2 -- one part, never a split."""
+    range holding it with ratio >= 1/f -- one part, never a split."""
     for r in range(n):
         for (l, rr) in ((0, r), (r, n - 1)):
-            parts, cnt = oracle.select(n, leaf, l, rr)
+            parts, cnt = oracle.select(n, leaf, l, rr, c_den=f, fanout=f)
             assert cnt == 1
             p = parts[0]
             if p["kind"] == oracle.KIND_GRAPH:
-                assert 2 * (p["y"] - p["x"] + 1) >= p["b"] - p["a"] + 1
+                assert f * (p["y"] - p["x"] + 1) >= p["b"] - p["a"] + 1
 
 
-@pytest.mark.parametrize("n,leaf", [(20, 1), (37, 2), (64, 4)])
-def test_elastic_factor_definition(n, leaf):
+@pytest.mark.parametrize("n,leaf,f", [(20, 1, 2), (37, 2, 2), (64, 4, 2), (50, 1, 4), (70, 2, 8)])
+def test_elastic_factor_definition(n, leaf, f):
     """Def. 3.1: e(R,[l,r]) is the best ratio over recorded supersets.
     Brute force over the recorded ranges R of the tree; and a graph part
-    chosen by Alg. 4 never has a ratio below 1/2."""
-    R = [(a, b) for _, _, a, b, g in tree_nodes(n, leaf) if g]
+    chosen by Alg. 4 never has a ratio below 1/f."""
+    R = [(a, b) for _, _, a, b, g in tree_nodes(n, leaf, f) if g]
     for l in range(n):
         for r in range(l, n):
             best = None
@@ -104,7 +137,7 @@ def test_elastic_factor_definition(n, leaf):
                 if a <= l and r <= b:
                     fr = (r - l + 1) / (b - a + 1)
                     best = fr if best is None else max(best, fr)
-            num, den = oracle.elastic_factor(n, leaf, l, r)
+            num, den = oracle.elastic_factor(n, leaf, l, r, fanout=f)
             if best is None:
                 assert den == 0
             else:
