@@ -20,14 +20,21 @@ against exact ground truth (the library's brute-force scan) is >= 0.95:
   learned_batched    the same with the per-part beam width (or stopping
                      step) predicted by the network trained here on traces
                      of 200,000 separate training queries (GPU kernels).
-Settings are swept on the evaluation queries for every form alike (a
-QPS/recall frontier).  K steps of the learned form are timed and give
-`value`; the other two are reported beside it.  One JSON line is printed.
+Every form's setting (its ef, or the network's calibration offset delta)
+is chosen on a held-out calibration set: 50,000 queries of the same shape
+from their own seed streams (7000+c for vectors, 8000+c for ranges), as the
+cheapest setting whose calibration recall reaches 0.95 plus a margin of
+three standard errors of that mean (sd of the per-query recall over the
+square root of 50,000: about 0.002).  Recall and QPS are
+then measured on the evaluation queries.  K steps of the fastest form whose
+evaluation recall is >= 0.95 are timed and give `value`; the others are
+reported beside it.  One JSON line is printed.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -40,6 +47,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 TARGET_RECALL = 0.95
+CAL_QUERIES = 50_000
+CAL_SE = 3.0          # calibration margin in standard errors of the mean recall
 EF_GRID = [10, 12, 14, 16, 18, 20, 22, 24, 28, 32, 40, 48, 64, 96, 100, 112, 128, 192, 256, 384, 512, 768, 1024]
 DELTA_GRID = [-1.0, -0.75, -0.5, -0.375, -0.25, -0.125, 0.0, 0.25, 0.5]
 LABEL_EF_GRID = [10, 12, 14, 16, 18, 20, 22, 24, 28, 32, 40, 48, 64, 96, 128, 192, 256]
@@ -61,7 +70,8 @@ def parse():
     ap.add_argument("--nq", type=int, default=None, help="shrink the query count")
     ap.add_argument("--ntrain", type=int, default=200_000, help="training traces")
     ap.add_argument("--ef-max", type=int, default=32, help="beam of the learned form")
-    ap.add_argument("--probe-hops", type=int, default=4)
+    ap.add_argument("--probe-hops", type=int, nargs="+", default=[1, 4],
+                    help="probe lengths of the learned form (one network each)")
     ap.add_argument("--reps", type=int, default=5, help="timed repetitions per sweep point")
     ap.add_argument("--cache-dir", default=os.environ.get("ESG_BENCH_CACHE", "/tmp/esg_bench"))
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -79,6 +89,11 @@ def parse():
     ap.add_argument("--scan-only", action="store_true",
                     help="time only the exact MFMA range scan over the workload's queries "
                          "(MFMA roofline), print one JSON line and exit")
+    ap.add_argument("--fanout", type=int, default=2, help="segment-tree fanout of the index")
+    ap.add_argument("--fanout-sweep", action="store_true",
+                    help="build the index at fanout 2, 4, 8, 16 and report graph memory, "
+                         "build time and plain-search QPS at recall >= 0.95 for the workload's "
+                         "range mix and for fixed 2^-5 N ranges; print one JSON line and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory 5 times and exit (calibrates the "
                          "HBM byte counters against a transfer of known size)")
@@ -131,6 +146,210 @@ def stored_traffic(key):
     return None
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(args, path, w, k, ef, gt_ids):
+    """The oracle as it stands, timed on the host cores: the same float32
+    beam search over a bounded sample of the evaluation queries with all
+    cores (OpenMP over queries) and with one thread (the paper's
+    single-threaded search, Section 5.1), and the float64 brute force of
+    Def. 2.2 on a sample.  The brute-force sample also cross-checks the
+    GPU's ground truth (the exact scan): tie-aware recall of its top k
+    against float64."""
+    import ctypes
+    import oracle
+    oix = oracle.read_index(path)
+    gomp = ctypes.CDLL("libgomp.so.1")
+    threads = int(gomp.omp_get_max_threads())
+    nq = len(w["Q"])
+    budget = args.cpu_seconds / 3.0
+
+    def timed(fn, chunk, limit):
+        done, el = 0, 0.0
+        while done < limit and el < budget:
+            m = min(chunk, limit - done)
+            s0 = time.perf_counter()
+            fn(done, m)
+            el += time.perf_counter() - s0
+            done += m
+        return done, el
+
+    search = lambda s, m: oracle.query_batch(oix, w["Q"][s:s + m], w["l"][s:s + m],
+                                             w["r"][s:s + m], k, ef)
+    n_mt, t_mt = timed(search, 1000, nq)
+    gomp.omp_set_num_threads(1)
+    n_st, t_st = timed(search, 100, nq)
+    gomp.omp_set_num_threads(threads)
+    bf = {}
+
+    def brute(s, m):
+        bf[s] = oracle.bruteforce(oix.vec, w["Q"][s:s + m], w["l"][s:s + m], w["r"][s:s + m], k)
+    n_bf, t_bf = timed(brute, 200, nq)
+    # ground-truth cross-check on the brute-forced sample
+    pos_of = np.empty(oix.n, np.int64)
+    pos_of[oix.ext_id] = np.arange(oix.n)
+    gi = gt_ids[:n_bf]
+    found = np.where(gi >= 0, pos_of[np.maximum(gi, 0)], -1)
+    gp = np.concatenate([bf[s][0] for s in sorted(bf)])
+    gd = np.concatenate([bf[s][1] for s in sorted(bf)])
+    rec, strict, _ = oracle.recall(oix.vec, w["Q"][:n_bf], w["l"][:n_bf], w["r"][:n_bf], found,
+                                   gp, gd, k)
+    log(f"cpu oracle {n_mt / t_mt:,.0f} q/s on {threads} threads, {n_st / t_st:,.0f} q/s on one; "
+        f"float64 brute force {n_bf / t_bf:,.1f} q/s; scan ground truth vs float64: {rec}")
+    return {"value": round(n_mt / t_mt, 1), "unit": "queries/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"first {n_mt} of the {nq} evaluation queries (chunks of 1000, about "
+                      f"{budget:.0f}s), the same float32 beam search at the plain point "
+                      f"ef={ef}, OpenMP over queries; {t_mt:.1f}s",
+            "single_thread": {"value": round(n_st / t_st, 1), "unit": "queries/s",
+                              "sample": f"first {n_st} queries, one thread, {t_st:.1f}s"},
+            "bruteforce_f64": {"value": round(n_bf / t_bf, 2), "unit": "queries/s",
+                               "cores": threads, "seconds": round(t_bf, 2),
+                               "sample": f"first {n_bf} queries, exact float64 filtered k-NN"},
+            "gt_check": {"queries": int(n_bf), "recall_of_scan_vs_f64": rec,
+                         "strict": strict}}
+
+
+def load_index(args, cid, w, fanout):
+    import paper_2504_04018_amd as esg
+    import synth
+    os.makedirs(args.cache_dir, exist_ok=True)
+    n = w["n"]
+    tag = synth.sha256_of(w["X"][:1000], w["attr"][:1000])[:12]
+    path = os.path.join(args.cache_dir,
+                        f"{args.workload}_{n}_R{w['degree']}_f{fanout}_{tag}.esgi")
+    build_s = None
+    if not os.path.exists(path):
+        t0 = time.time()
+        esg.build_index(w["X"], w["attr"].astype(np.float64), path + ".tmp", degree=w["degree"],
+                        leaf=w["leaf"], ef_construction=w["ef_construction"], verbose=True,
+                        fanout=fanout)
+        os.replace(path + ".tmp", path)
+        build_s = time.time() - t0
+        log(f"index (fanout {fanout}) built in {build_s:.1f}s")
+    return path, build_s
+
+
+class Bench:
+    """Evaluation and calibration query sets with their exact answers, and
+    the measurement of one setting on each."""
+
+    def __init__(self, args, ix, w, wc, dev):
+        import torch
+        from paper_2504_04018_amd import learned
+        self.args, self.ix, self.k = args, ix, w["k"]
+        self.dev = dev
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        self.Q, self.l, self.r = t(w["Q"]), t(w["l"]), t(w["r"])
+        self.Qc, self.lc, self.rc = t(wc["Q"]), t(wc["l"]), t(wc["r"])
+        self.width, self.widthc = self.r - self.l + 1, self.rc - self.lc + 1
+        t0 = time.time()
+        self.gt_ids, self.gt_d = learned.exact_answers(ix, self.Q, self.l, self.r, self.k)
+        _, self.gt_dc = learned.exact_answers(ix, self.Qc, self.lc, self.rc, self.k)
+        torch.cuda.synchronize()
+        log(f"exact ground truth (MFMA scan) of {len(self.Q)} + {len(self.Qc)} queries in "
+            f"{time.time() - t0:.1f}s")
+        self.nq = len(self.Q)
+        self.ids = torch.empty((self.nq, self.k), dtype=torch.int64, device=dev)
+        self.dists = torch.empty((self.nq, self.k), dtype=torch.float32, device=dev)
+        self.sweep = []
+
+    def recall(self, ids, dists, cal=False):
+        from paper_2504_04018_amd import learned
+        gt, wd = (self.gt_dc, self.widthc) if cal else (self.gt_d, self.width)
+        return float(learned.per_query_recall(ids, dists, gt, wd, self.k).mean().item())
+
+    def cal_recall(self, ef, kw, with_se=False):
+        from paper_2504_04018_amd import learned
+        kw = {kk: v for kk, v in kw.items() if kk != "use_graph"}
+        ids, dists = self.ix.search_ex(self.Qc, self.lc, self.rc, self.k, ef, **kw)
+        per = learned.per_query_recall(ids, dists, self.gt_dc, self.widthc, self.k)
+        mean = float(per.mean().item())
+        if with_se:
+            return mean, float(per.std().item()) / math.sqrt(per.numel())
+        return mean
+
+    def qps(self, ef, kw):
+        from paper_2504_04018_amd import autotune
+        sec = autotune.time_call(lambda: self.ix.search_ex(self.Q, self.l, self.r, self.k, ef,
+                                                           ids=self.ids, dists=self.dists, **kw),
+                                 self.args.reps)
+        return self.nq / sec
+
+    def evaluate(self, variant, ef, kw, cal_rec, **extra):
+        self.ix.search_ex(self.Q, self.l, self.r, self.k, ef, ids=self.ids, dists=self.dists, **kw)
+        rec = self.recall(self.ids, self.dists)
+        q = self.qps(ef, kw)
+        row = dict(variant=variant, ef=ef, traversal=kw.get("traversal", "f32"),
+                   cal_recall=round(cal_rec, 5), recall=round(rec, 5), qps=round(q, 1), **extra)
+        self.sweep.append(row)
+        log(f"{variant} ef={ef} {extra} calibration recall={cal_rec:.4f} "
+            f"evaluation recall={rec:.4f} qps={q:,.0f}")
+        return row
+
+    def pick(self, candidates):
+        """First candidate (cheapest first) whose calibration recall reaches
+        the target plus CAL_SE standard errors; each candidate's function
+        returns (mean recall, standard error).  Returns (value, recall)."""
+        last = None
+        for val, fn in candidates:
+            rec, se = fn()
+            last = (val, rec)
+            if rec >= TARGET_RECALL + CAL_SE * se:
+                return last
+        return last
+
+
+def fanout_sweep(args, cid, dev):
+    """Graph memory, build time and plain float32 QPS at recall >= 0.95 per
+    fanout (Section 4.2, Extensions; the paper's Exp-6)."""
+    import torch
+    import paper_2504_04018_amd as esg
+    from paper_2504_04018_amd import learned
+    import synth
+    w = synth.make_workload(cid, n=args.n, nq=args.nq)
+    wc = synth.make_workload(cid, n=args.n, nq=CAL_QUERIES, query_stream=7000, range_stream=8000)
+    del wc["X"]
+    n, k = w["n"], w["k"]
+    lf, rf = synth.fixed_width_ranges(n, len(w["Q"]), 2.0 ** -5, 9000 + cid)
+    lfc, rfc = synth.fixed_width_ranges(n, CAL_QUERIES, 2.0 ** -5, 9500 + cid)
+    rows = []
+    for f in (2, 4, 8, 16):
+        path, build_s = load_index(args, cid, w, f)
+        ix = esg.Index(path, 0)
+        ix.add_storage("bf16")
+        ix.reserve(max(len(w["Q"]), CAL_QUERIES), 262144)
+        info = ix.info()
+        row = {"fanout": f, "n_depth": info["n_depth"],
+               "graph_bytes": int(info["n_depth"] * n * info["degree"] * 4),
+               "build_s": None if build_s is None else round(build_s, 1)}
+        for name, (l, r, lc, rc) in {"mix": (w["l"], w["r"], wc["l"], wc["r"]),
+                                     "fixed_2^-5N": (lf, rf, lfc, rfc)}.items():
+            wv = dict(w, l=l, r=r)
+            wcv = dict(wc, l=lc, r=rc)
+            b = Bench(args, ix, wv, wcv, dev)
+            ef, cr = b.pick([(ef, (lambda e=ef: b.cal_recall(e, {}, True)))
+                             for ef in EF_GRID if ef >= k])
+            ev = b.evaluate(f"plain_f32_f{f}_{name}", ef, {}, cr)
+            row[name] = {"ef": ef, "cal_recall": ev["cal_recall"], "recall": ev["recall"],
+                         "qps": ev["qps"]}
+            del b
+            torch.cuda.empty_cache()
+        rows.append(row)
+        ix.free()
+        log(f"fanout {f}: {row}")
+    print(json.dumps({"fanout_sweep": rows, "workload": w["name"], "n": n, "k": k,
+                      "queries": len(w["Q"]), "calibration_queries": CAL_QUERIES}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -155,37 +374,27 @@ def main():
     cid = {"deep": 2, "sift": 1, "embedding": 3}[args.workload]
     if cid == 3 and args.n is None:
         args.n = 200_000
+    if args.fanout_sweep:
+        fanout_sweep(args, cid, dev)
+        return
     t0 = time.time()
     w = synth.make_workload(cid, n=args.n, nq=args.nq)
+    wc = synth.make_workload(cid, n=args.n, nq=CAL_QUERIES, query_stream=7000, range_stream=8000)
+    del wc["X"]
     n, d, k = w["n"], w["d"], w["k"]
     nq = len(w["Q"])
-    log(f"workload {w['name']} n={n} d={d} nq={nq} generated in {time.time() - t0:.1f}s")
-    os.makedirs(args.cache_dir, exist_ok=True)
-    tag = synth.sha256_of(w["X"][:1000], w["attr"][:1000])[:12]
-    path = os.path.join(args.cache_dir, f"{args.workload}_{n}_R{w['degree']}_{tag}.esgi")
-    if not os.path.exists(path):
-        t0 = time.time()
-        esg.build_index(w["X"], w["attr"].astype(np.float64), path + ".tmp", degree=w["degree"],
-                        leaf=w["leaf"], ef_construction=w["ef_construction"], verbose=True)
-        os.replace(path + ".tmp", path)
-        log(f"index built in {time.time() - t0:.1f}s")
+    log(f"workload {w['name']} n={n} d={d} nq={nq} (+{CAL_QUERIES} calibration) generated in "
+        f"{time.time() - t0:.1f}s")
+    path, _ = load_index(args, cid, w, args.fanout)
     X = w.pop("X")                        # kept for the float64 distance check
     ix = esg.Index(path, 0)
     ix.add_storage("bf16")
     if cid == 3:
         ix.add_storage("fp8")
-    ix.reserve(max(nq, args.ntrain), 262144)
+    ix.reserve(max(nq, args.ntrain, CAL_QUERIES), 262144)
     info = ix.info()
-
-    def dev_t(a):
-        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-
-    Q, l, r = dev_t(w["Q"]), dev_t(w["l"]), dev_t(w["r"])
-    width = r - l + 1
-    t0 = time.time()
-    gt_ids, gt_d = learned.exact_answers(ix, Q, l, r, k)
-    torch.cuda.synchronize()
-    log(f"exact ground truth (MFMA scan) in {time.time() - t0:.1f}s")
+    B = Bench(args, ix, w, wc, dev)
+    Q, l, r, width = B.Q, B.l, B.r, B.width
 
     if args.scan_only:
         # exact scan: algorithmic flops 2*w*d per query (in-range points only)
@@ -208,115 +417,100 @@ def main():
                           "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4), "n_fallback": int(nfb)}))
         return
 
-    def recall(ids, dists):
-        return float(learned.per_query_recall(ids, dists, gt_d, width, k).mean().item())
-
-    ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
-    dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
-    sweep = []
-
-    def point(variant, ef, kw, **extra):
-        ix.search_ex(Q, l, r, k, ef, ids=ids, dists=dists, **kw)
-        rec = recall(ids, dists)
-        sec = autotune.time_call(lambda: ix.search_ex(Q, l, r, k, ef, ids=ids, dists=dists, **kw),
-                                 args.reps)
-        row = dict(variant=variant, ef=ef, traversal=kw.get("traversal", "f32"),
-                   recall=round(rec, 5), qps=round(nq / sec, 1), **extra)
-        sweep.append(row)
-        log(f"{variant} ef={ef} {extra} recall={rec:.4f} qps={nq / sec:,.0f}")
-        return row
-
-    def best_of(rows):
-        ok = [s for s in rows if s["recall"] >= TARGET_RECALL]
-        return max(ok, key=lambda s: s["qps"]) if ok else None
-
-    def fixed_sweep(variant, kw):
-        rows, hits = [], 0
-        for ef in ([args.fixed_ef] if args.fixed_ef else EF_GRID):
-            if ef < k:
-                continue
-            rows.append(point(variant, ef, kw))
-            hits += rows[-1]["recall"] >= TARGET_RECALL
-            if hits >= 3:                      # QPS only falls from here on
-                break
-        return best_of(rows) or max(rows, key=lambda s: s["recall"])
+    def ef_candidates(kw):
+        grid = [args.fixed_ef] if args.fixed_ef else [e for e in EF_GRID if e >= k]
+        return [(e, (lambda e=e: B.cal_recall(e, kw, True))) for e in grid]
 
     # ---- plain: float32 traversal, fixed ef -------------------------------------
     plain_kw = dict(traversal="f32")
-    plain_best = fixed_sweep("plain_f32", plain_kw)
+    ef_p, cr = B.pick(ef_candidates(plain_kw))
+    plain_best = B.evaluate("plain_f32", ef_p, plain_kw, cr)
 
-    # ---- batched + bfloat16, fixed ef, autotuned launch settings --------------------
+    # ---- batched, fixed ef, autotuned launch settings --------------------------------
     fixed_best = learned_best = train_info = None
-    lkw = None
+    learned_rows = []
+    bkw = None
     if not args.plain_only:
-        base = dict(rerank=True, use_graph=True)
-        tuned, _ = autotune.tune(
-            ix, Q, l, r, k, plain_best["ef"], base, recall, 0.0,
-            grid={"traversal": [args.traversal] if args.traversal else
-                  (["fp8", "bf16", "f32"] if cid == 3 else ["bf16", "f32"]),
-                  "router_threshold": [args.router] if args.router is not None else [0, 512, 2048],
-                  "hash_cap": [args.hash_cap] if args.hash_cap else [4096, 8192]},
-            reps=args.reps, log=log)
+        base = dict(use_graph=True)
+        grid = {"traversal": [args.traversal] if args.traversal else
+                (["fp8", "bf16", "f32"] if cid == 3 else ["bf16", "f32"]),
+                "router_threshold": [args.router] if args.router is not None else [0, 512, 2048],
+                "hash_cap": [args.hash_cap] if args.hash_cap else [4096, 8192]}
+
+        def measure(kw):
+            kw = dict(kw, rerank=kw["traversal"] != "f32")
+            return B.cal_recall(ef_p, kw), B.qps(ef_p, kw)
+        # knobs that keep the recall of the plain point (within 0.002) may be
+        # traded for speed; the beam itself is calibrated afterwards
+        tuned, _ = autotune.tune_settings(base, grid, measure, cr - 0.002, log=log)
         tuned["rerank"] = tuned["traversal"] != "f32"
         bkw = {kk: tuned[kk] for kk in ("traversal", "rerank", "use_graph", "router_threshold",
                                          "hash_cap")}
-        fixed_best = fixed_sweep("fixed_batched", bkw)
+        ef_f, cr = B.pick(ef_candidates(bkw))
+        fixed_best = B.evaluate("fixed_batched", ef_f, bkw, cr)
 
     if not args.plain_only and args.ef_max < k:
         log(f"learned form skipped: --ef-max {args.ef_max} < k = {k}")
     elif not args.plain_only:
         # ---- learned: traces of separate training queries, GPU training ------------------
-        t0 = time.time()
         wt = synth.make_workload(cid, n=n, nq=args.ntrain, query_stream=5000, range_stream=6000)
         del wt["X"]
-        Qt, lt, rt = dev_t(wt["Q"]), dev_t(wt["l"]), dev_t(wt["r"])
+        tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        Qt, lt, rt = tt(wt["Q"]), tt(wt["l"]), tt(wt["r"])
         _, gt_dt = learned.exact_answers(ix, Qt, lt, rt, k)
         tkw = {kk: v for kk, v in bkw.items() if kk != "use_graph"}
         train_info = {}
-        cands = []
-        for target, grid in (("ef", LABEL_EF_GRID), ("hops", LABEL_HOP_GRID)):
-            if args.target and target != args.target:
-                continue
-            t1 = time.time()
-            g = [v for v in grid if target == "hops" or v <= args.ef_max]
-            F, T = learned.traces(ix, Qt, lt, rt, k, g, args.ef_max, args.probe_hops, tkw, gt_dt,
-                                  target=target)
-            params, hist = learned.train(F, T)
-            train_info[target] = dict(traces=int(F.shape[0]), queries=args.ntrain,
-                                      first_mse=round(hist[0], 4), final_mse=round(hist[-1], 4),
-                                      seconds=round(time.time() - t1, 2))
-            log(f"learned target={target}: {F.shape[0]} part traces, mse {hist[0]:.3f} -> "
-                f"{hist[-1]:.3f} in {time.time() - t1:.1f}s")
-            cands.append((target, params))
-            del F, T
+        nets = []
+        for probe in args.probe_hops:
+            for target, grid in (("ef", LABEL_EF_GRID), ("hops", LABEL_HOP_GRID)):
+                if args.target and target != args.target:
+                    continue
+                t1 = time.time()
+                g = [v for v in grid if target == "hops" or v <= args.ef_max]
+                F, T = learned.traces(ix, Qt, lt, rt, k, g, args.ef_max, probe, tkw, gt_dt,
+                                      target=target)
+                params, hist = learned.train(F, T)
+                train_info[f"{target}_probe{probe}"] = dict(
+                    traces=int(F.shape[0]), queries=args.ntrain, first_mse=round(hist[0], 4),
+                    final_mse=round(hist[-1], 4), seconds=round(time.time() - t1, 2))
+                log(f"learned target={target} probe={probe}: {F.shape[0]} part traces, mse "
+                    f"{hist[0]:.3f} -> {hist[-1]:.3f} in {time.time() - t1:.1f}s")
+                nets.append((target, probe, params))
+                del F, T
         del Qt, lt, rt, gt_dt
-        # the network is evaluated with the tuned traversal and with the other one
         travs = [bkw["traversal"]] + ([] if args.traversal else
                                       [t for t in ("bf16", "f32") if t != bkw["traversal"]])
-        rows = []
-        for target, params in cands:
+        for target, probe, params in nets:
             for trav in travs:
                 kw = dict(bkw, traversal=trav, rerank=trav != "f32", mlp=params,
-                          probe_hops=args.probe_hops, mlp_target=1 if target == "hops" else 0)
-                for delta in ([args.delta] if args.delta is not None else DELTA_GRID):
-                    rows.append(point("learned_batched", args.ef_max, dict(kw, mlp_delta=delta),
-                                      delta=delta, target=target))
-        learned_best = best_of(rows)
-        if learned_best is not None:
-            trav = learned_best["traversal"]
-            lkw = dict(bkw, traversal=trav, rerank=trav != "f32",
-                       mlp=dict(cands)[learned_best["target"]], probe_hops=args.probe_hops,
-                       mlp_target=1 if learned_best["target"] == "hops" else 0,
-                       mlp_delta=learned_best["delta"])
+                          probe_hops=probe, mlp_target=1 if target == "hops" else 0)
+                deltas = [args.delta] if args.delta is not None else DELTA_GRID
+                dl, cr = B.pick([(dv, (lambda dv=dv: B.cal_recall(args.ef_max,
+                                                                  dict(kw, mlp_delta=dv), True)))
+                                 for dv in deltas])
+                kw["mlp_delta"] = dl
+                row = B.evaluate("learned_batched", args.ef_max, kw, cr, delta=dl, target=target,
+                                 probe_hops=probe)
+                learned_rows.append((row, kw))
+        ok = [(rw, kw) for rw, kw in learned_rows if rw["recall"] >= TARGET_RECALL]
+        if ok:
+            learned_best, lkw = max(ok, key=lambda t: t[0]["qps"])
 
     # ---- operating point and timed region -----------------------------------------
-    if lkw is not None:
-        mode, ef, kw, best = "learned_batched", args.ef_max, lkw, learned_best
-    elif fixed_best is not None and fixed_best["recall"] >= TARGET_RECALL:
-        mode, ef, kw, best = "fixed_batched", fixed_best["ef"], dict(bkw), fixed_best
+    forms = [("plain_f32", plain_best["ef"], dict(plain_kw), plain_best)]
+    if fixed_best is not None:
+        forms.append(("fixed_batched", fixed_best["ef"], dict(bkw), fixed_best))
+    if learned_best is not None:
+        forms.append(("learned_batched", args.ef_max, lkw, learned_best))
+    # the learned + batched form is the one the metric names; without it, the
+    # fastest form whose evaluation recall reaches the target
+    ok = [f for f in forms if f[3]["recall"] >= TARGET_RECALL]
+    if learned_best is not None:
+        mode, ef, kw, best = forms[-1]
     else:
-        mode, ef, kw, best = "plain_f32", plain_best["ef"], dict(plain_kw), plain_best
+        mode, ef, kw, best = max(ok or forms[:1], key=lambda f: f[3]["qps"])
     log(f"operating point: {mode} {best}")
+    ids, dists = B.ids, B.dists
     for _ in range(args.warmup):
         ix.search_ex(Q, l, r, k, ef, ids=ids, dists=dists, **kw)
     torch.cuda.synchronize()
@@ -327,16 +521,16 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1000.0 / args.steps
     qps = nq / (ms_per_step / 1000.0)
-    rec_timed = recall(ids, dists)
+    rec_timed = B.recall(ids, dists)
     # float32 distances returned against float64 ones over the returned points
     samp = np.arange(0, nq, max(1, nq // 500))
     ids_h, d_h = ids[samp].cpu().numpy(), dists[samp].cpu().numpy()
     rel = []
     for i, qi in enumerate(samp):
-        ok = ids_h[i] >= 0
-        diff = X[ids_h[i][ok]].astype(np.float64) - w["Q"][qi].astype(np.float64)
+        ok_ = ids_h[i] >= 0
+        diff = X[ids_h[i][ok_]].astype(np.float64) - w["Q"][qi].astype(np.float64)
         d64 = (diff * diff).sum(1)
-        rel.append(np.abs(d_h[i][ok].astype(np.float64) - d64) / np.maximum(d64, 1e-30))
+        rel.append(np.abs(d_h[i][ok_].astype(np.float64) - d64) / np.maximum(d64, 1e-30))
     rel = np.concatenate(rel) if rel else np.zeros(1)
     dist_err = {"max_rel": float(rel.max()), "mean_rel": float(rel.mean()),
                 "queries": int(len(samp))}
@@ -379,27 +573,23 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        oix = oracle.read_index(path)
-        done, el, chunk = 0, 0.0, 1000
-        while done < nq and el < args.cpu_seconds:
-            m = min(chunk, nq - done)
-            s0 = time.perf_counter()
-            oracle.query_batch(oix, w["Q"][done:done + m], w["l"][done:done + m],
-                               w["r"][done:done + m], k, plain_best["ef"])
-            el += time.perf_counter() - s0
-            done += m
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cpu = {"value": round(done / el, 1), "unit": "queries/s", "cores": cores, "kind": "oracle",
-               "sample": f"first {done} of the {nq} queries (chunks of {chunk} until "
-                         f"{args.cpu_seconds:.0f}s), plain float32 search at the plain point "
-                         f"ef={plain_best['ef']}, OpenMP over queries; {el:.1f}s"}
-        log(f"cpu oracle {done / el:,.0f} q/s on {cores} cores over {done} queries")
+        cpu = cpu_baseline(args, path, w, k, plain_best["ef"], B.gt_ids.cpu().numpy())
 
     wl = {2: f"deep-shaped N={n} d={d} unit-norm, {nq} queries, widths log-uniform 10..N, k={k}",
           1: f"sift-shaped N={n} d={d} uint8-valued, {nq} queries, 11 width buckets 2^-b*N, k={k}",
           3: f"embedding-shaped N={n} d={d} unit-norm, {nq} queries, 13 width buckets 2^-b*N, "
              f"k={k}"}[cid]
+    lb16 = [rw_ for rw_, _ in learned_rows if rw_["traversal"] == "bf16"
+            and rw_["recall"] >= TARGET_RECALL]
+    best16 = max(lb16, key=lambda t: t["qps"]) if lb16 else None
+    target = {
+        "statement": "learned + batched + bfloat16 beats plain float32 fixed-ef (and fixed-ef "
+                     "bfloat16 batched) at recall@10 >= 0.95",
+        "learned_bf16_qps": best16["qps"] if best16 else None,
+        "learned_bf16_recall": best16["recall"] if best16 else None,
+        "beats_plain_f32": bool(best16 and best16["qps"] > plain_best["qps"]),
+        "beats_fixed_batched": bool(best16 and fixed_best and best16["qps"] > fixed_best["qps"]),
+    }
     out = {
         "metric": "QPS at recall@10>=0.95, learned+batched vs plain search, 1 MI355X; HBM GB/s"
                   if k == 10 else f"QPS at recall@{k}>=0.95, 1 MI355X; HBM GB/s",
@@ -417,17 +607,21 @@ def main():
         "config": {"workload": wl, "variant": mode, f"recall_at_{k}": round(rec_timed, 5),
                    "traversal": kw.get("traversal", "f32"), "distance_error_vs_f64": dist_err,
                    "ef": ef, "delta": best.get("delta"), "target": best.get("target"),
+                   "probe_hops": best.get("probe_hops"),
                    "router_threshold": kw.get("router_threshold", 0),
-                   "hash_cap": kw.get("hash_cap", 0), "probe_hops": args.probe_hops,
-                   "leaf": info["leaf"], "degree": info["degree"], "n_depth": info["n_depth"]},
+                   "hash_cap": kw.get("hash_cap", 0), "fanout": info["fanout"],
+                   "leaf": info["leaf"], "degree": info["degree"], "n_depth": info["n_depth"],
+                   "calibration": {"queries": CAL_QUERIES, "query_seed": 7000 + cid,
+                                   "range_seed": 8000 + cid, "margin_se": CAL_SE}},
         "plain_f32": plain_best,
         "fixed_batched": fixed_best,
         "learned_batched": learned_best,
+        "target": target,
         "speedup_vs_plain": round(qps / plain_best["qps"], 3),
         "learned_gain_vs_fixed": (round(learned_best["qps"] / fixed_best["qps"], 3)
                                   if learned_best and fixed_best else None),
         "training": train_info,
-        "sweep": sweep,
+        "sweep": B.sweep,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "search_kernel", "kernel_ms": round(kern_ms, 4),

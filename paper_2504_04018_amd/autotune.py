@@ -1,5 +1,8 @@
 """Autotuner for the batched search: times candidate launch settings on a
 sample batch and keeps the fastest one whose recall meets the target.
+``tune_settings`` takes the recall and the throughput of a setting from a
+caller-supplied measurement (so recall can come from held-out calibration
+queries while the throughput is timed on the batch itself).
 
 Knobs: LDS visited-hash capacity (waves per CU against spills to the global
 bitmap), router threshold (narrow ranges to the MFMA scan), and the
@@ -41,6 +44,27 @@ def tune(ix, Q, l, r, k, ef, base_kw, recall_fn, target, grid=None, reps=3, log=
         if log:
             log(f"tune {row}")
         if rec >= target and (best is None or row["qps"] > best[1]["qps"]):
+            best = (kw, row)
+    if best is None:
+        best = max(((dict(base_kw, **{k_: r_[k_] for k_ in keys}), r_) for r_ in table),
+                   key=lambda t: t[1]["recall"])
+    return best[0], table
+
+
+def tune_settings(base_kw, grid, measure, target, log=None):
+    """Every combination of the grid's knobs on top of base_kw; measure(kw)
+    returns (recall, qps).  Returns (best_kw, table): the fastest setting
+    whose recall reaches target (else the most accurate one)."""
+    keys = list(grid)
+    table, best = [], None
+    for vals in itertools.product(*(grid[k_] for k_ in keys)):
+        kw = dict(base_kw, **dict(zip(keys, vals)))
+        rec, qps = measure(kw)
+        row = dict(zip(keys, vals), recall=round(rec, 5), qps=round(qps, 1))
+        table.append(row)
+        if log:
+            log(f"tune {row}")
+        if rec >= target and (best is None or qps > best[1]["qps"]):
             best = (kw, row)
     if best is None:
         best = max(((dict(base_kw, **{k_: r_[k_] for k_ in keys}), r_) for r_ in table),

@@ -330,8 +330,9 @@ constexpr int kSpillLog = 4096;   // logged bitmap words per wave slot
 
 struct Visited {
   uint32_t* table;   // T/2 words of two 16-bit slots
-  uint32_t* bm;      // spill bitmap of this wave slot, indexed by position - a
-  uint32_t* log;     // [kSpillLog] bitmap words set during the current part
+  uint32_t* bm;      // spill bitmap of this wave slot, indexed by position - a; its
+                     // log (kSpillLog words set during the current part) follows at
+                     // bm + spill_words
   uint32_t a, b;
   uint32_t kb_mask;  // 2^kb - 1
   int kb, shift;     // shift = kb - log2(T) (stored low bits)
@@ -345,11 +346,12 @@ __device__ __forceinline__ uint32_t vkey_mix(uint32_t k, const Visited& V) {
 
 // End of a part: clears the bitmap words its spilled keys set, leaving the
 // bitmap all zero for the next part.
-__device__ __forceinline__ void visited_finish(Visited& V, int lane) {
+__device__ __forceinline__ void visited_finish(const SearchArgs& A, Visited& V, int lane) {
   if (V.nlog == 0) return;
   __threadfence();   // every lane's log entries and bitmap updates are visible
   if (V.nlog <= kSpillLog) {
-    for (int i = lane; i < V.nlog; i += kWave) V.bm[V.log[i]] = 0u;
+    const uint32_t* log = V.bm + A.spill_words;
+    for (int i = lane; i < V.nlog; i += kWave) V.bm[log[i]] = 0u;
   } else {
     const uint32_t words = ((V.b - V.a) >> 5) + 1u;
     for (uint32_t i = (uint32_t)lane; i < words; i += kWave) V.bm[i] = 0u;
@@ -397,7 +399,7 @@ __device__ __forceinline__ bool visit(const SearchArgs& A, Visited& V, uint32_t 
       const uint32_t bit = 1u << (off & 31u);
       is_new = (atomicOr(&V.bm[off >> 5], bit) & bit) == 0u;
       const int at = V.nlog + rank_below(om);
-      if (at < kSpillLog) V.log[at] = off >> 5;
+      if (at < kSpillLog) V.bm[A.spill_words + at] = off >> 5;
     }
     V.nlog += __popcll(om);
   }
@@ -445,6 +447,7 @@ struct Desc {
 };
 
 __device__ __forceinline__ int64_t child_begin(int64_t a, int64_t L, int32_t f, int64_t j) {
+  if (f == 2) return a + ((j * L + 1) >> 1);
   return a + (j * L + f - 1) / f;
 }
 
@@ -456,8 +459,15 @@ __device__ __forceinline__ bool descend(Desc& it, int64_t leaf, int32_t c_den, i
     const bool is_leaf = it.b - it.a < leaf;
     const bool elastic = !is_leaf && (int64_t)c_den * (it.y - it.x + 1) >= L;
     if (is_leaf || elastic) return true;
-    const int64_t jx = (int64_t)fanout * (it.x - it.a) / L;
-    const int64_t jy = (int64_t)fanout * (it.y - it.a) / L;
+    int64_t jx, jy;
+    if (fanout == 2) {                      // Alg. 4's split at floor((a+b)/2), no division
+      const int64_t mid = (it.a + it.b) >> 1;
+      jx = it.x > mid;
+      jy = it.y > mid;
+    } else {
+      jx = (int64_t)fanout * (it.x - it.a) / L;
+      jy = (int64_t)fanout * (it.y - it.a) / L;
+    }
     const int64_t h0 = (int64_t)fanout * (it.heap - 1) + 2;
     const int64_t s0 = child_begin(it.a, L, fanout, jx), s1 = child_begin(it.a, L, fanout, jx + 1);
     if (jy == jx) {

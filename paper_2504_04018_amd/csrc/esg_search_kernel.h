@@ -305,7 +305,7 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
   if (go)
     while (hop(false)) {
     }
-  visited_finish(V, lane);
+  visited_finish(A, V, lane);
   return {hops, nvis};
 }
 
@@ -467,7 +467,6 @@ void search_kernel(SearchArgs A) {
   Visited V;
   V.table = wave_table(Ls);
   V.bm = A.spill + slot * (A.spill_words + kSpillLog);
-  V.log = V.bm + A.spill_words;
   V.a = V.b = 0;
   V.kb = V.shift = 0;
   V.kb_mask = 0;

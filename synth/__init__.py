@@ -30,7 +30,7 @@ import math
 
 import numpy as np
 
-__all__ = ["Workload", "WORKLOADS", "make_workload", "sha256_of"]
+__all__ = ["Workload", "WORKLOADS", "make_workload", "fixed_width_ranges", "sha256_of"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -147,6 +147,16 @@ def make_workload(cid: int, n: int | None = None, nq: int | None = None,
     return dict(workload=w, name=w.name, n=n, d=w.d, X=X, attr=attr, Q=Q,
                 l=l, r=r, k=w.k, ef=w.ef, leaf=w.leaf, degree=w.degree,
                 ef_construction=w.ef_construction)
+
+
+def fixed_width_ranges(n: int, nq: int, frac: float, seed: int):
+    """nq ranges of width floor(n * frac) at uniform random offsets (the
+    fixed-length ranges of the paper's experiments, e.g. 2^-5 N)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    width = max(1, int(math.floor(n * frac)))
+    l = (rng.random(nq) * (n - width + 1)).astype(np.int64)
+    l = np.minimum(l, n - width)
+    return l, l + width - 1
 
 
 def sha256_of(*arrays: np.ndarray) -> str:
