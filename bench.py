@@ -326,7 +326,7 @@ def fanout_sweep(args, cid, dev):
         path, build_s = load_index(args, cid, w, f)
         ix = esg.Index(path, 0)
         ix.add_storage("bf16")
-        ix.reserve(max(len(w["Q"]), CAL_QUERIES), 262144)
+        ix.reserve(max(len(w["Q"]), CAL_QUERIES), 4_500_000)
         info = ix.info()
         row = {"fanout": f, "n_depth": info["n_depth"],
                "graph_bytes": int(info["n_depth"] * n * info["degree"] * 4),
@@ -391,7 +391,7 @@ def main():
     ix.add_storage("bf16")
     if cid == 3:
         ix.add_storage("fp8")
-    ix.reserve(max(nq, args.ntrain, CAL_QUERIES), 262144)
+    ix.reserve(max(nq, args.ntrain, CAL_QUERIES), 4_500_000)
     info = ix.info()
     B = Bench(args, ix, w, wc, dev)
     Q, l, r, width = B.Q, B.l, B.r, B.width

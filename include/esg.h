@@ -228,11 +228,14 @@ typedef struct {
 } esg_search_opts;
 
 /* Reserves the device workspace of the brute-force scan and the router:
- * per-query lists for up to max_queries queries per call and buffers for
- * up to max_windows windows of at most 2,048 positions (about 10 KB per
- * window).  Calls with more queries or windows return ERANGE (the router)
- * or are split into several passes (esg_scan_batch).  Allocates; call it
- * once before searching.  Errors: EINVAL, ENOMEM. */
+ * per-query lists for up to max_queries queries per call and per-window
+ * records for up to max_windows windows of at most 2,048 positions (about
+ * 540 bytes per window).  A window's candidate list takes 64E slots of the
+ * 64 reserved per window (E = 1, 2, 4 for k <= 32, 64, 128), so a call
+ * handles max_windows / E windows at once: esg_scan_batch splits larger
+ * batches into several passes, the router returns ERANGE.  Also holds the
+ * one-hop learned form's per-part buffers.  Allocates; call it once before
+ * searching.  Errors: EINVAL, ENOMEM. */
 int32_t esg_index_reserve(esg_index* idx, int64_t max_queries, int64_t max_windows);
 
 typedef struct {

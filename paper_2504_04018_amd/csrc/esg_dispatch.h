@@ -11,8 +11,7 @@ constexpr int kNumScanWidths = 3;  // scan candidate lists of 64, 128, 256 keys
 struct KernelTable {
   int dim;
   const void* fn[kNumKinds][kNumWidths][3];   // [.][.][0] plain, [1] one-hop probe, [2] longer probe
-  const void* mfma;                       // MFMA approximate distances
-  const void* select[kNumScanWidths];     // per-window top list
+  const void* scan_select[kNumScanWidths];  // MFMA distances + per-window top list
   const void* rerank[kNumScanWidths];     // merge + float32 rerank + certificate
   const void* fallback[kNumScanWidths];   // exact float32 scan of each window
   const void* fb_merge[kNumScanWidths];   // merge of the windows' exact lists

@@ -87,8 +87,7 @@ struct esg_index {
   int32_t* wide = nullptr;
   int32_t* counts = nullptr;    // [0] narrow, [1] wide, [2] fallback, [3..] bucket histogram
   int32_t* fb_list = nullptr;
-  float* dist_buf = nullptr;
-  uint64_t* cand = nullptr;
+  uint64_t* cand = nullptr;      // [res_windows * 64] per-window candidate lists
   int nbuckets = 0, bucket_shift = 11;
   hipStream_t capture_stream = nullptr;
   struct GraphEntry {
@@ -586,8 +585,7 @@ int32_t esg_index_reserve(esg_index* idx, int64_t max_queries, int64_t max_windo
   A((void**)&idx->wide, Q * 4);
   A((void**)&idx->fb_list, Q * 4);
   A((void**)&idx->counts, (size_t)(4 + idx->nbuckets) * 4);
-  A((void**)&idx->dist_buf, W * esgk::kWin * 4);
-  A((void**)&idx->cand, W * 256 * 8);
+  A((void**)&idx->cand, W * 64 * 8);
   if (st != ESG_OK) return st;
   if (hipStreamCreateWithFlags(&idx->capture_stream, hipStreamNonBlocking) != hipSuccess)
     return ESG_EHIP;
@@ -624,9 +622,8 @@ esgk::ScanArgs scan_args(esg_index* idx, const float* queries, const int64_t* l,
   S.win_order = idx->win_order;
   S.q_win0 = idx->q_win0;
   S.q_nwin = idx->q_nwin;
-  S.dist_buf = idx->dist_buf;
   S.cand = idx->cand;
-  S.cand_stride = 256;
+  S.cand_stride = 64 << scan_width_index(k);
   S.ids = ids;
   S.dists = dists;
   S.fb_list = idx->fb_list;
@@ -649,12 +646,11 @@ int32_t launch_fn(const void* fn, int64_t grid, size_t lds, void* arg, hipStream
   return ESG_OK;
 }
 
-// The four scan kernels over windows already described in the workspace.
+// The scan kernels over windows already described in the workspace.
 int32_t launch_scan(esg_index* idx, esgk::ScanArgs& S, int64_t nw_bound, int64_t nq_bound,
                     hipStream_t s) {
   const int wi = scan_width_index(S.k);
-  int32_t st = launch_fn(idx->kt->mfma, (nw_bound + 63) / 64, 0, &S, s);
-  if (st == ESG_OK) st = launch_fn(idx->kt->select[wi], (nw_bound + 3) / 4, 0, &S, s);
+  int32_t st = launch_fn(idx->kt->scan_select[wi], (nw_bound + 63) / 64, 0, &S, s);
   if (st == ESG_OK)
     st = launch_fn(idx->kt->rerank[wi], (nq_bound + 3) / 4, 4 * esgk::kStageBytes, &S, s);
   // fallback: the window pass takes every resident wave slot (the windows of
@@ -670,13 +666,52 @@ int32_t launch_scan(esg_index* idx, esgk::ScanArgs& S, int64_t nw_bound, int64_t
 
 }  // namespace
 
+namespace {
+
+// ---- 0. windows on the device --------------------------------------------------
+// Query i (listed in qlist) owns windows q_win0[i] .. + q_nwin[i] - 1 (the
+// host computed both); window j covers [l + j kWin, min(r, l + (j+1) kWin - 1)].
+__global__ void scan_expand_kernel(esgk::ScanArgs S) {
+  using esgk::kWin;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= S.nq_list) return;
+  const int32_t qi = S.qlist ? S.qlist[t] : (int32_t)t;
+  const int64_t a = S.l[qi], b = S.r[qi];
+  const int32_t w0 = S.q_win0[qi], nwq = S.q_nwin[qi];
+  for (int32_t j = 0; j < nwq; j++) {
+    S.win_q[w0 + j] = qi;
+    S.win_s[w0 + j] = a + (int64_t)j * kWin;
+    S.win_e[w0 + j] = (a + (int64_t)(j + 1) * kWin - 1) < b ? a + (int64_t)(j + 1) * kWin - 1 : b;
+  }
+}
+
+__global__ void set_i32_kernel(int32_t* p, int32_t v) { *p = v; }
+
+void scan_expand_kernel_launch(const esgk::ScanArgs& S, hipStream_t s) {
+  if (S.nq_list > 0)
+    scan_expand_kernel<<<(unsigned)((S.nq_list + 255) / 256), 256, 0, s>>>(S);
+}
+
+// win_order = the windows 0..counts[0]-1 in buckets of 2^bucket_shift start
+// positions, ascending (histogram, exclusive scan, scatter)
+void sort_windows_by_start(esg_index* idx, int64_t nw_bound, hipStream_t s) {
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (nw_bound + 255) / 256));
+  bucket_hist_kernel<<<grid, 256, 0, s>>>(idx->win_s, idx->counts, idx->bucket_shift,
+                                          idx->counts + 4);
+  bucket_scan_kernel<<<1, 1024, 0, s>>>(idx->counts + 4, idx->nbuckets);
+  bucket_scatter_kernel<<<grid, 256, 0, s>>>(idx->win_s, idx->counts, idx->bucket_shift,
+                                             idx->counts + 4, idx->win_order);
+}
+
+}  // namespace
+
 int32_t esg_scan_batch(esg_index* idx, const esg_scan_opts* opts, const float* queries,
                        const int64_t* l, const int64_t* r, int64_t nq, int32_t k, int64_t* ids,
                        float* dists, void* stream) {
   if (!idx || nq < 0) return ESG_EINVAL;
   if (nq == 0) return ESG_OK;
   if (!queries || !l || !r || !ids || !dists || k < 1 || k > 128) return ESG_EINVAL;
-  if (!idx->vec16 || !idx->norm2 || !idx->kt->mfma) return ESG_EUNSUPPORTED;
+  if (!idx->vec16 || !idx->norm2 || !idx->kt->scan_select[0]) return ESG_EUNSUPPORTED;
   if (idx->res_queries < 1) return ESG_ERANGE;
   if (nq > idx->res_queries) return ESG_ERANGE;
   esg_scan_opts o;
@@ -693,55 +728,46 @@ int32_t esg_scan_batch(esg_index* idx, const esg_scan_opts* opts, const float* q
       hipMemcpyAsync(hr.data(), r, (size_t)nq * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return ESG_EHIP;
-  std::vector<int32_t> q0((size_t)nq, 0), qn((size_t)nq, 0);
+  // windows per query on the host (O(nq)); expansion and the sort by start
+  // run on the device
+  // a window's list takes 64E 64-bit slots of the 64 reserved per window
+  const int64_t cap_windows = idx->res_windows / (1 << scan_width_index(k));
+  std::vector<int32_t> q0((size_t)nq, 0), qn((size_t)nq, 0), qlist;
   int64_t n_fallback = 0;
   int64_t qa = 0;
   while (qa < nq) {
     // one pass: queries [qa, qb) whose windows fit the reservation
-    std::vector<int32_t> wq, order, qlist;
-    std::vector<int64_t> wsv, wev;
-    int64_t qb = qa;
+    int64_t qb = qa, nw = 0;
+    qlist.clear();
     for (; qb < nq; qb++) {
       const int64_t a = hl[(size_t)qb], b = hr[(size_t)qb];
       const bool valid = a >= 0 && b < idx->n && a <= b;
       const int64_t nwq = valid ? (b - a + esgk::kWin) / esgk::kWin : 0;
-      if ((int64_t)wq.size() + nwq > idx->res_windows && qb > qa) break;
-      if (nwq > idx->res_windows) return ESG_ERANGE;
-      q0[(size_t)qb] = (int32_t)wq.size();
+      if (nw + nwq > cap_windows && qb > qa) break;
+      if (nwq > cap_windows) return ESG_ERANGE;
+      q0[(size_t)qb] = (int32_t)nw;
       qn[(size_t)qb] = (int32_t)nwq;
-      for (int64_t j = 0; j < nwq; j++) {
-        wq.push_back((int32_t)qb);
-        wsv.push_back(a + j * esgk::kWin);
-        wev.push_back(std::min(b, a + (j + 1) * esgk::kWin - 1));
-      }
+      nw += nwq;
       qlist.push_back((int32_t)qb);
     }
-    const int64_t nw = (int64_t)wq.size();
-    order.resize((size_t)nw);
-    for (int64_t i = 0; i < nw; i++) order[(size_t)i] = (int32_t)i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t u, int32_t v) { return wsv[(size_t)u] < wsv[(size_t)v]; });
-    bool ok = true;
-    if (nw > 0)
-      ok = hipMemcpyAsync(idx->win_q, wq.data(), nw * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
-           hipMemcpyAsync(idx->win_s, wsv.data(), nw * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
-           hipMemcpyAsync(idx->win_e, wev.data(), nw * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
-           hipMemcpyAsync(idx->win_order, order.data(), nw * 4, hipMemcpyHostToDevice, s) ==
-               hipSuccess;
-    ok = ok &&
-         hipMemcpyAsync(idx->q_win0, q0.data(), (size_t)nq * 4, hipMemcpyHostToDevice, s) ==
-             hipSuccess &&
-         hipMemcpyAsync(idx->q_nwin, qn.data(), (size_t)nq * 4, hipMemcpyHostToDevice, s) ==
-             hipSuccess &&
-         hipMemcpyAsync(idx->qlist, qlist.data(), qlist.size() * 4, hipMemcpyHostToDevice, s) ==
-             hipSuccess;
+    bool ok = hipMemcpyAsync(idx->q_win0, q0.data(), (size_t)nq * 4, hipMemcpyHostToDevice, s) ==
+                  hipSuccess &&
+              hipMemcpyAsync(idx->q_nwin, qn.data(), (size_t)nq * 4, hipMemcpyHostToDevice, s) ==
+                  hipSuccess &&
+              hipMemcpyAsync(idx->qlist, qlist.data(), qlist.size() * 4, hipMemcpyHostToDevice,
+                             s) == hipSuccess;
     if (!ok) return ESG_EHIP;
-    zero_i32_kernel<<<1, 64, 0, s>>>(idx->counts, 4);
     esgk::ScanArgs S = scan_args(idx, queries, l, r, nq, k, mr, ids, dists, o.certified);
     S.force_exact = (o.flags & ESG_SCAN_EXACT) ? 1 : 0;
     S.qlist = idx->qlist;
     S.nw = nw;
     S.nq_list = (int64_t)qlist.size();
+    S.win_order = idx->win_order;
+    zero_i32_kernel<<<1, 1024, 0, s>>>(idx->counts, 4 + idx->nbuckets);
+    set_i32_kernel<<<1, 1, 0, s>>>(idx->counts, (int32_t)nw);
+    scan_expand_kernel_launch(S, s);
+    sort_windows_by_start(idx, nw, s);
+    S.n_win_dev = nullptr;
     int32_t st = launch_scan(idx, S, nw, (int64_t)qlist.size(), s);
     if (st != ESG_OK) return st;
     int32_t nfb = 0;
@@ -843,7 +869,8 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   if (o.router_threshold > 0) {
     if (!idx->vec16 || !idx->norm2) return ESG_EUNSUPPORTED;
     if (k > 128) return ESG_EINVAL;
-    if (nq > idx->res_queries || nq > idx->res_windows) return ESG_ERANGE;
+    if (nq > idx->res_queries || nq > idx->res_windows / (1 << scan_width_index(k)))
+      return ESG_ERANGE;
     if (o.router_threshold > esgk::kWin) return ESG_EINVAL;
     const int cap = 64 << scan_width_index(k);
     mr = o.scan_rerank > 0 ? o.scan_rerank : cap - 1;

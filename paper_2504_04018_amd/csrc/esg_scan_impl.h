@@ -2,24 +2,31 @@
 //
 // The exact answer of Def. 2.2 for a query is the top k of its range by
 // the float32 canonical distance (ties by position).  The scan gets it in
-// four kernels:
-//  1. mfma_dist: one wave per block of 16 windows (a window is at most
-//     kWin consecutive positions of one query's range; windows are sorted by
-//     start so a block's windows overlap).  The wave walks the block's union
-//     span in tiles of 16 positions; v_mfma_f32_16x16x32_bf16 forms the dot
-//     products of 16 points with the 16 window queries (bfloat16 inputs,
-//     float32 accumulation); approx = |x|^2 + |q|^2 - 2 x.q (norms in float32
-//     from the float32 data) is written for every (window, position) pair
-//     inside the window.
-//  2. select: one wave per window keeps the 64*E smallest approx keys.
-//  3. rerank: one wave per query merges its windows' lists, recomputes the
+// three steps:
+//  1. scan_select: a query range is cut into windows of at most kWin
+//     consecutive positions, and the windows of the batch are sorted by
+//     start.  One workgroup (4 waves) takes 64 consecutive windows, 16 per
+//     wave, and walks the union of their spans in tiles of TP positions: the
+//     tile's bfloat16 vectors and norms are staged once in LDS for all 64
+//     windows, v_mfma_f32_16x16x32_bf16 forms the dot products of 16 points
+//     with a wave's 16 window queries (float32 accumulation), and
+//     approx = |x|^2 + |q|^2 - 2 x.q.  Each window keeps its 64E smallest
+//     approx values: a value below the window's current bound is appended to
+//     the window's LDS buffer, and a full buffer is merged into the window's
+//     sorted list (registers, bitonic) which lowers the bound.  Values are
+//     32-bit keys: the approx bits with their low 11 mantissa bits replaced
+//     by the offset in the window, so a key never exceeds the float it
+//     came from (truncation toward zero keeps the certificate below
+//     conservative).  Each window writes its list.
+//  2. rerank: one wave per query merges its windows' lists, recomputes the
 //     first m_r candidates with the float32 canonical distance and keeps the
 //     top k.  The result is certified exact when the k-th float32 distance is
-//     below (A - eps)(1 - g) / (1 + g), A being the (m_r+1)-th smallest approx
-//     distance, eps the bound on |approx - exact| (bfloat16 rounding of x and
-//     q, float32 accumulation and norms) and g a float32 relative error bound:
-//     then no point outside the candidates can enter the top k.
-//  4. fallback: queries that are not certified are rescanned exactly
+//     below (A - eps)(1 - g) / (1 + g), A being the value of the (m_r+1)-th
+//     smallest key (no unreranked point has a smaller approx), eps the bound
+//     on |approx - exact| (bfloat16 rounding of x and q, float32
+//     accumulation and norms) and g a float32 relative error bound: then no
+//     point outside the candidates can enter the top k.
+//  3. fallback: queries that are not certified are rescanned exactly
 //     (float32 canonical distances): each window's exact top k, one wave
 //     per window, then one merge per query.
 #pragma once
@@ -28,7 +35,9 @@
 
 namespace esgk {
 
-constexpr int kWin = 2048;  // longest window scored by one select wave
+constexpr int kWin = 2048;        // longest window; offsets fit the key's 11 low bits
+constexpr int kScanWinPerWave = 16;
+constexpr int kScanBuf = 128;     // LDS candidate buffer per window
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
@@ -46,9 +55,9 @@ struct ScanArgs {
   int64_t nq;
   int32_t k, mr;           // results per query, candidates reranked
   // windows (sorted by start for the MFMA kernel)
-  const int32_t* win_q;    // [nw] query of each window
-  const int64_t* win_s;    // [nw] first position
-  const int64_t* win_e;    // [nw] last position
+  int32_t* win_q;          // [nw] query of each window
+  int64_t* win_s;          // [nw] first position
+  int64_t* win_e;          // [nw] last position
   const int32_t* win_order;// [nw] windows sorted by start (mfma) ; null = identity
   const int32_t* q_win0;   // [nq] first window of each query (windows of a query are consecutive)
   const int32_t* q_nwin;   // [nq] number of windows of each query
@@ -56,9 +65,9 @@ struct ScanArgs {
   const int32_t* n_win_dev;// device count of windows (null: use nw)
   const int32_t* n_q_dev;  // device count of listed queries (null: use nq_list)
   int64_t nw, nq_list;
-  float* dist_buf;         // [nw][kWin] approx distances
-  uint64_t* cand;          // [nw][64*E] selected keys per window
-  int64_t cand_stride;
+  uint64_t* cand;          // [nw][cand_stride]: 64E 32-bit keys of the MFMA pass, or the
+                           // exact 64-bit keys of the fallback
+  int64_t cand_stride;     // in 64-bit slots, >= 64E
   // outputs
   int64_t* ids;            // [nq][k]
   float* dists;            // [nq][k]
@@ -78,31 +87,91 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   return (uint16_t)(b >> 16);
 }
 
-// Non-negative float as a sortable key (negative approximations clamp to 0).
-__device__ __forceinline__ uint64_t approx_key(float a, uint32_t pos) {
-  return make_key(a > 0.0f ? a : 0.0f, pos);
+// Window key: approx (negative values clamp to 0) with the low 11 mantissa
+// bits replaced by the offset in the window.  Its value as a float is <= the
+// approx.
+__device__ __forceinline__ uint32_t win_key(float a, uint32_t off) {
+  return ((__float_as_uint(a > 0.0f ? a : 0.0f)) & ~0x7FFu) | off;
+}
+// The 64-bit candidate key (truncated approx bits, position) of a window key.
+__device__ __forceinline__ uint64_t cand_key(uint32_t wk, int64_t ws) {
+  return wk == 0xFFFFFFFFu ? kKeyInf
+                           : ((uint64_t)(wk & ~0x7FFu) << 32) | (uint64_t)(ws + (wk & 0x7FFu));
 }
 
-// ---- 1. MFMA distances ------------------------------------------------------
-template <int NK>  // dp / 32 rounded up: 32-wide K chunks
-__global__ __launch_bounds__(256) void mfma_dist_kernel(ScanArgs S) {
+// ---- 32-bit ordered lists across a wave (element i: word i/64, lane i%64) ----
+
+__device__ __forceinline__ uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint32_t umax32(uint32_t a, uint32_t b) { return a < b ? b : a; }
+
+// Ascending bitonic sort of one key per lane.
+__device__ __forceinline__ uint32_t sort64_u32(uint32_t v, int lane) {
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j >= 1; j >>= 1) {
+      const uint32_t p = xor_u32(v, j, lane);
+      const bool up = (lane & k) == 0;
+      const bool lower = (lane & j) == 0;
+      v = (lower == up) ? umin32(v, p) : umax32(v, p);
+    }
+  }
+  return v;
+}
+
+// Keeps the 64E smallest of the sorted list L and the sorted batch b (one
+// key per lane): min against the reversed batch, then a bitonic finish.
+template <int E>
+__device__ __forceinline__ void merge64_u32(uint32_t (&L)[E], uint32_t b, int lane) {
+  L[E - 1] = umin32(L[E - 1], bperm(b, 63 - lane));
+#pragma unroll
+  for (int s = E / 2; s >= 1; s >>= 1) {
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      if ((e & s) == 0) {
+        const uint32_t lo = umin32(L[e], L[e + s]), hi = umax32(L[e], L[e + s]);
+        L[e] = lo;
+        L[e + s] = hi;
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) {
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const uint32_t p = xor_u32(L[e], s, lane);
+      L[e] = (lane & s) ? umax32(L[e], p) : umin32(L[e], p);
+    }
+  }
+}
+
+// ---- 1. MFMA distances and per-window selection --------------------------------------
+template <int NK, int E, int TP, int DP>
+__global__ __launch_bounds__(256) void scan_select_kernel(ScanArgs S) {
+  constexpr int ROW = DP + 8;                  // padded LDS row (bf16 elements)
+  constexpr int NWG = 4 * kScanWinPerWave;     // windows per workgroup
+  constexpr int CAP = 64 * E;                  // list length per window
+  __shared__ __align__(16) uint16_t tile[TP * ROW];
+  __shared__ float tnorm[TP];
+  __shared__ uint32_t buf[4][kScanWinPerWave][kScanBuf];
+  __shared__ int32_t cnt[4][kScanWinPerWave];
+  __shared__ int64_t span[4][2];
   const int lane = lane_id();
+  const int wave = (int)(threadIdx.x >> 6);
   const int64_t nw = S.n_win_dev ? *S.n_win_dev : S.nw;
-  const int64_t block = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t w0 = block * 16;
-  if (w0 >= nw) return;
+  const int64_t wbase = (int64_t)blockIdx.x * NWG;
+  if (wbase >= nw) return;                     // uniform over the workgroup
   const int col = lane & 15;   // window (B column) and point (A row) index in the tile
   const int grp = lane >> 4;   // K group of 8 within a 32-wide chunk
-  // this lane's window (column)
-  const int64_t wi = w0 + col;
+  const int64_t wi = wbase + wave * kScanWinPerWave + col;
   const bool wvalid = wi < nw;
   const int32_t wid = wvalid ? (S.win_order ? S.win_order[wi] : (int32_t)wi) : 0;
   const int32_t qid = wvalid ? S.win_q[wid] : 0;
   const int64_t ws = wvalid ? S.win_s[wid] : 0, we = wvalid ? S.win_e[wid] : -1;
-  // query operand (B): bfloat16 of q[32c + 8*grp .. +7]
+  // query operand (B): bfloat16 of q[32c + 8*grp .. +7]; |q|^2 in float32
   bf16x8_t qb[NK];
-  float qn = 0.0f;
   const float* q = S.queries + (int64_t)qid * S.d;
+  float qn = 0.0f;
 #pragma unroll
   for (int c = 0; c < NK; c++) {
 #pragma unroll
@@ -110,113 +179,132 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(ScanArgs S) {
       const int j = 32 * c + 8 * grp + e;
       const float v = (wvalid && j < S.d) ? q[j] : 0.0f;
       qb[c][e] = __builtin_bit_cast(__bf16, f32_to_bf16_rne(v));
+      qn = __builtin_fmaf(v, v, qn);
     }
   }
-  // |q|^2 in float32 (each lane sums its 8*NK values; the 4 groups add)
-  {
-    float s = 0.0f;
-#pragma unroll
-    for (int c = 0; c < NK; c++)
-#pragma unroll
-      for (int e = 0; e < 8; e++) {
-        const int j = 32 * c + 8 * grp + e;
-        const float v = (wvalid && j < S.d) ? q[j] : 0.0f;
-        s = __builtin_fmaf(v, v, s);
-      }
-    s += xor_f(s, 16, lane);
-    s += xor_f(s, 32, lane);
-    qn = s;
-  }
-  // union span of the block
-  int64_t lo = wvalid ? ws : INT64_MAX, hi = wvalid ? we : -1;
+  qn += xor_f(qn, 16, lane);
+  qn += xor_f(qn, 32, lane);
+  // workgroup span: each wave reduces its 16 windows, then the 4 waves'
+  int64_t wlo = wvalid ? ws : INT64_MAX, whi = wvalid ? we : -1;
 #pragma unroll
   for (int s = 1; s < 16; s <<= 1) {
-    const int64_t olo = (int64_t)(((uint64_t)xor_u32((uint32_t)(lo >> 32), s, lane) << 32) |
-                                  xor_u32((uint32_t)lo, s, lane));
-    const int64_t ohi = (int64_t)(((uint64_t)xor_u32((uint32_t)(hi >> 32), s, lane) << 32) |
-                                  xor_u32((uint32_t)hi, s, lane));
-    lo = olo < lo ? olo : lo;
-    hi = ohi > hi ? ohi : hi;
+    const int64_t olo = (int64_t)(((uint64_t)xor_u32((uint32_t)(wlo >> 32), s, lane) << 32) |
+                                  xor_u32((uint32_t)wlo, s, lane));
+    const int64_t ohi = (int64_t)(((uint64_t)xor_u32((uint32_t)(whi >> 32), s, lane) << 32) |
+                                  xor_u32((uint32_t)whi, s, lane));
+    wlo = olo < wlo ? olo : wlo;
+    whi = ohi > whi ? ohi : whi;
   }
-  lo = (int64_t)readlane64((uint64_t)lo, 0);
-  hi = (int64_t)readlane64((uint64_t)hi, 0);
-  if (hi < lo) return;
-  // query norms of the 16 columns, for the output layout below
-  const float qn_col = qn;  // lane's own column (lanes col, col+16, ... hold the same value)
-  float* dbuf = S.dist_buf + (int64_t)wid * kWin;
-  const uint16_t* X = S.vec16;
-  for (int64_t t0 = lo & ~(int64_t)15; t0 <= hi; t0 += 16) {
-    // skip tiles no window of the block touches (blocks may straddle gaps)
-    const bool touch = wvalid && ws <= t0 + 15 && we >= t0;
-    if (ballot(touch) == 0) {
-      int64_t nxt = (wvalid && we >= t0 + 16) ? (ws > t0 + 16 ? ws : t0 + 16) : INT64_MAX;
-#pragma unroll
-      for (int s = 1; s < 16; s <<= 1) {
-        const int64_t o = (int64_t)(((uint64_t)xor_u32((uint32_t)(nxt >> 32), s, lane) << 32) |
-                                    xor_u32((uint32_t)nxt, s, lane));
-        nxt = o < nxt ? o : nxt;
-      }
-      nxt = (int64_t)readlane64((uint64_t)nxt, 0);
-      if (nxt == INT64_MAX) break;
-      t0 = (nxt & ~(int64_t)15) - 16;
-      continue;
-    }
-    // A operand: point t0 + col, dims 32c + 8*grp .. +7
-    const int64_t prow = t0 + col;
-    const bool prow_ok = prow < S.n;
-    f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int c = 0; c < NK; c++) {
-      const int j0 = 32 * c + 8 * grp;
-      uint4 raw = make_uint4(0, 0, 0, 0);
-      if (prow_ok && j0 < S.dp) raw = *reinterpret_cast<const uint4*>(X + prow * S.dp + j0);
-      const bf16x8_t a = __builtin_bit_cast(bf16x8_t, raw);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, qb[c], acc, 0, 0, 0);
-    }
-    // D layout: lane holds rows (points) 4*grp + i, column (window) col
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int64_t p = t0 + 4 * grp + i;
-      if (wvalid && p >= ws && p <= we) {
-        const float ap = S.norm2[p] + qn_col - 2.0f * acc[i];
-        dbuf[p - ws] = ap;
-      }
-    }
+  if (lane == 0) {
+    span[wave][0] = wlo;
+    span[wave][1] = whi;
   }
-}
+  if (threadIdx.x < 4 * kScanWinPerWave) (&cnt[0][0])[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t lo = span[0][0], hi = span[0][1];
+#pragma unroll
+  for (int v = 1; v < 4; v++) {
+    lo = span[v][0] < lo ? span[v][0] : lo;
+    hi = span[v][1] > hi ? span[v][1] : hi;
+  }
+  uint32_t L[kScanWinPerWave][E];
+#pragma unroll
+  for (int w = 0; w < kScanWinPerWave; w++)
+#pragma unroll
+    for (int e = 0; e < E; e++) L[w][e] = 0xFFFFFFFFu;
+  uint32_t tau = 0xFFFFFFFFu;                  // this lane's window: keys below enter its buffer
+  int32_t* mycnt = &cnt[wave][col];
+  uint32_t* mybuf = buf[wave][col];
 
-// ---- 2. per-window selection ----------------------------------------------------
-template <int E>
-__global__ __launch_bounds__(256) void select_kernel(ScanArgs S) {
-  const int lane = lane_id();
-  const int64_t nw = S.n_win_dev ? *S.n_win_dev : S.nw;
-  const int64_t wi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wi >= nw) return;
-  const int32_t wid = S.win_order ? S.win_order[wi] : (int32_t)wi;
-  const int64_t ws = S.win_s[wid], we = S.win_e[wid];
-  const int w = (int)(we - ws + 1);
-  const float* dbuf = S.dist_buf + (int64_t)wid * kWin;
-  uint64_t L[E];
-  list_clear(L);
-  constexpr int cap = kWave * E;
-  for (int base = 0; base < w; base += kBatch) {
-    const int i = base + lane;
-    uint64_t key = (lane < kBatch && i < w) ? approx_key(dbuf[i], (uint32_t)(ws + i)) : kKeyInf;
-    const uint64_t worst = list_at(L, cap - 1);
-    if (worst != kKeyInf && worst < key) key = kKeyInf;
-    const uint64_t sm = ballot(key != kKeyInf);
-    if (sm == 0) continue;
-    if (__popcll(sm) <= 4) {
-      for (uint64_t mm = sm; mm; mm &= mm - 1)
-        list_insert(L, readlane64(key, __builtin_ctzll(mm)), cap, lane);
-    } else {
-      key = sort32(key, lane);
-      list_merge32(L, bperm64(key, 63 - lane), cap, lane);
+  // merges the buffers of the windows in `need` into their lists
+  auto flush = [&](uint32_t need) {
+#pragma unroll
+    for (int w = 0; w < kScanWinPerWave; w++) {
+      if (need & (1u << w)) {
+        const int c = cnt[wave][w];
+        for (int b0 = 0; b0 < c; b0 += 64) {
+          uint32_t v = b0 + lane < c ? buf[wave][w][b0 + lane] : 0xFFFFFFFFu;
+          v = sort64_u32(v, lane);
+          merge64_u32<E>(L[w], v, lane);
+        }
+        const uint32_t bound = readlane(L[w][E - 1], 63);
+        if (col == w) tau = bound;
+      }
+    }
+    wave_lds_sync();
+    if (lane < kScanWinPerWave && (need & (1u << lane))) cnt[wave][lane] = 0;
+    wave_lds_sync();
+  };
+
+  for (int64_t t0 = lo & ~(int64_t)(TP - 1); t0 <= hi; t0 += TP) {
+    // skip tiles no window of the workgroup touches
+    const bool touch = wvalid && ws <= t0 + TP - 1 && we >= t0;
+    if (!__syncthreads_or(touch)) continue;
+    // stage the tile's vectors and norms
+    constexpr int CH = DP / 8;                 // 16-byte chunks per row
+    for (int u = (int)threadIdx.x; u < TP * CH; u += 256) {
+      const int row = u / CH, ch = u % CH;
+      const int64_t p = t0 + row;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (p < S.n) v = *reinterpret_cast<const uint4*>(S.vec16 + p * S.dp + ch * 8);
+      *reinterpret_cast<uint4*>(&tile[row * ROW + ch * 8]) = v;
+    }
+    if (threadIdx.x < TP) {
+      const int64_t p = t0 + threadIdx.x;
+      tnorm[threadIdx.x] = p < S.n ? S.norm2[p] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sub = 0; sub < TP / 16; sub++) {
+      f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int c = 0; c < NK; c++) {
+        const int j0 = 32 * c + 8 * grp;
+        uint4 raw = make_uint4(0, 0, 0, 0);
+        if (j0 < DP) raw = *reinterpret_cast<const uint4*>(&tile[(sub * 16 + col) * ROW + j0]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, raw), qb[c],
+                                                     acc, 0, 0, 0);
+      }
+      // D layout: this lane holds points sub*16 + 4*grp + i of window col
+      uint32_t keys[4];
+      int nk = 0;
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int r = sub * 16 + 4 * grp + i;
+        const int64_t p = t0 + r;
+        const float ap = tnorm[r] + qn - 2.0f * acc[i];
+        const uint32_t key = win_key(ap, (uint32_t)(p - ws));
+        const bool take = wvalid && p >= ws && p <= we && key < tau;
+        keys[i] = key;
+        nk += take ? 1 : 0;
+        if (!take) keys[i] = 0xFFFFFFFFu;
+      }
+      if (nk > 0) {
+        int at = atomicAdd(mycnt, nk);
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+          if (keys[i] != 0xFFFFFFFFu) mybuf[at++] = keys[i];
+      }
+    }
+    __syncthreads();                           // buffer counts complete, tile reusable
+    // windows whose buffer could overflow during the next tile are merged now
+    const uint32_t need =
+        (uint32_t)ballot(lane < kScanWinPerWave && cnt[wave][lane] > kScanBuf - TP) & 0xFFFFu;
+    if (need) flush(need);
+  }
+  const uint32_t rest = (uint32_t)ballot(lane < kScanWinPerWave && cnt[wave][lane] > 0) & 0xFFFFu;
+  if (rest) flush(rest);
+  // write each valid window's list (64E 32-bit keys)
+#pragma unroll
+  for (int w = 0; w < kScanWinPerWave; w++) {
+    const int64_t wj = wbase + wave * kScanWinPerWave + w;
+    if (wj < nw) {
+      const int32_t id = S.win_order ? S.win_order[wj] : (int32_t)wj;
+      uint32_t* out = reinterpret_cast<uint32_t*>(S.cand + (int64_t)id * S.cand_stride);
+#pragma unroll
+      for (int e = 0; e < E; e++) out[e * kWave + lane] = L[w][e];
     }
   }
-  uint64_t* out = S.cand + (int64_t)wid * S.cand_stride;
-#pragma unroll
-  for (int e = 0; e < E; e++) out[e * kWave + lane] = L[e];
 }
 
 // ---- 3. merge, float32 rerank, certification ----------------------------------------
@@ -236,10 +324,11 @@ __global__ __launch_bounds__(256) void rerank_kernel(ScanArgs S) {
   list_clear(L);
   const int32_t w0 = S.q_win0[qi], nwq = S.q_nwin[qi];
   for (int32_t j = 0; j < nwq; j++) {
-    const uint64_t* c = S.cand + (int64_t)(w0 + j) * S.cand_stride;
+    const uint32_t* c = reinterpret_cast<const uint32_t*>(S.cand + (int64_t)(w0 + j) * S.cand_stride);
+    const int64_t wsj = S.win_s[w0 + j];
     uint64_t B[E];
 #pragma unroll
-    for (int e = 0; e < E; e++) B[e] = c[e * kWave + lane];
+    for (int e = 0; e < E; e++) B[e] = cand_key(c[e * kWave + lane], wsj);
     if (j == 0) {
 #pragma unroll
       for (int e = 0; e < E; e++) L[e] = B[e];
@@ -279,7 +368,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(ScanArgs S) {
   }
   // certification
   const uint64_t kth = list_at(R, k - 1);
-  const uint64_t next = mr < cap ? list_at(L, mr) : kKeyInf;  // (mr+1)-th approx key
+  const uint64_t next = mr < cap ? list_at(L, mr) : kKeyInf;  // (mr+1)-th key: a lower bound
   bool certified = true;
   if (next != kKeyInf && kth != kKeyInf) {
     // |approx - exact| <= 2 (dx + dq + dx dq) |x||q|            (bfloat16 rounding)

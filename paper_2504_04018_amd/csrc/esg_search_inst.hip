@@ -46,17 +46,19 @@ void fill(KernelTable* t) {
   fill_one<KIND, 2>(t);   // learned switch after a longer probe
 }
 
+constexpr int kDp = (ESG_DIM + 15) / 16 * 16;
+constexpr int kNK = (kDp + 31) / 32;
+// positions per LDS tile of the scan: the staged tile stays within 32 KB
+constexpr int kTP = kDp <= 128 ? 64 : (kDp <= 256 ? 32 : 16);
+
 template <int E>
 void fill_scan(KernelTable* t, int slot) {
   using S32 = Shape<kF32>;
-  t->select[slot] = reinterpret_cast<const void*>(&select_kernel<E>);
+  t->scan_select[slot] = reinterpret_cast<const void*>(&scan_select_kernel<kNK, E, kTP, kDp>);
   t->rerank[slot] = reinterpret_cast<const void*>(&rerank_kernel<S32::G, S32::CPL, E>);
   t->fallback[slot] = reinterpret_cast<const void*>(&fallback_window_kernel<S32::G, S32::CPL, E>);
   t->fb_merge[slot] = reinterpret_cast<const void*>(&fallback_merge_kernel<E>);
 }
-
-constexpr int kDp = (ESG_DIM + 15) / 16 * 16;
-constexpr int kNK = (kDp + 31) / 32;
 
 }  // namespace
 }  // namespace esgk
@@ -69,7 +71,6 @@ extern "C" void ESG_CAT(esg_register_dim_, ESG_DIM)(esgk::KernelTable* t) {
   esgk::fill<esgk::kF32>(t);
   esgk::fill<esgk::kBF16>(t);
   esgk::fill<esgk::kFP8>(t);
-  t->mfma = reinterpret_cast<const void*>(&esgk::mfma_dist_kernel<esgk::kNK>);
   esgk::fill_scan<1>(t, 0);
   esgk::fill_scan<2>(t, 1);
   esgk::fill_scan<4>(t, 2);
