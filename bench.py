@@ -94,6 +94,11 @@ def parse():
                     help="build the index at fanout 2, 4, 8, 16 and report graph memory, "
                          "build time and plain-search QPS at recall >= 0.95 for the workload's "
                          "range mix and for fixed 2^-5 N ranges; print one JSON line and exit")
+    ap.add_argument("--half-bounded", action="store_true",
+                    help="half-bounded queries (prefixes and suffixes, widths log-uniform 10..N) "
+                         "on the segment-tree index and on the prefix/suffix-chain index (the "
+                         "paper's half-bounded index): graph memory and plain-search QPS at "
+                         "recall >= 0.95; print one JSON line and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory 5 times and exit (calibrates the "
                          "HBM byte counters against a transfer of known size)")
@@ -218,20 +223,20 @@ def cpu_baseline(args, path, w, k, ef, gt_ids):
                          "strict": strict}}
 
 
-def load_index(args, cid, w, fanout):
+def load_index(args, cid, w, fanout, layout="tree"):
     import paper_2504_04018_amd as esg
     import synth
     os.makedirs(args.cache_dir, exist_ok=True)
     n = w["n"]
     tag = synth.sha256_of(w["X"][:1000], w["attr"][:1000])[:12]
     path = os.path.join(args.cache_dir,
-                        f"{args.workload}_{n}_R{w['degree']}_f{fanout}_{tag}.esgi")
+                        f"{args.workload}_{n}_R{w['degree']}_f{fanout}_{layout}_{tag}.esgi")
     build_s = None
     if not os.path.exists(path):
         t0 = time.time()
         esg.build_index(w["X"], w["attr"].astype(np.float64), path + ".tmp", degree=w["degree"],
                         leaf=w["leaf"], ef_construction=w["ef_construction"], verbose=True,
-                        fanout=fanout)
+                        fanout=fanout, layout=layout)
         os.replace(path + ".tmp", path)
         build_s = time.time() - t0
         log(f"index (fanout {fanout}) built in {build_s:.1f}s")
@@ -350,6 +355,54 @@ def fanout_sweep(args, cid, dev):
                       "queries": len(w["Q"]), "calibration_queries": CAL_QUERIES}), flush=True)
 
 
+def half_bounded(args, cid, dev):
+    """Half-bounded queries on the two index layouts (Section 4.1 against
+    Section 4.2): graph memory, build time, plain float32 QPS at recall >=
+    0.95 (ef calibrated on held-out half-bounded queries)."""
+    import torch
+    import paper_2504_04018_amd as esg
+    import synth
+    w = synth.make_workload(cid, n=args.n, nq=args.nq)
+    wc = synth.make_workload(cid, n=args.n, nq=CAL_QUERIES, query_stream=7000, range_stream=8000)
+    del wc["X"]
+    n, k = w["n"], w["k"]
+    w["l"], w["r"] = synth.half_bounded_ranges(n, len(w["Q"]), 10, 9100 + cid)
+    wc["l"], wc["r"] = synth.half_bounded_ranges(n, CAL_QUERIES, 10, 9600 + cid)
+    rows = []
+    for layout in ("tree", "chain"):
+        path, build_s = load_index(args, cid, w, 2, layout)
+        ix = esg.Index(path, 0)
+        ix.add_storage("bf16")
+        ix.reserve(max(len(w["Q"]), CAL_QUERIES), 4_500_000)
+        info = ix.info()
+        rows_per = (info["n_depth"] * n if layout == "tree"
+                    else 2 * sum(_chain_sizes(n, info["leaf"], 2)))
+        b = Bench(args, ix, w, wc, dev)
+        ef, cr = b.pick([(e, (lambda e=e: b.cal_recall(e, {}, True))) for e in EF_GRID if e >= k])
+        ev = b.evaluate(f"plain_f32_{layout}", ef, {}, cr)
+        rows.append({"layout": layout, "n_depth": info["n_depth"],
+                     "graph_bytes": int(rows_per * info["degree"] * 4),
+                     "build_s": None if build_s is None else round(build_s, 1),
+                     "ef": ef, "cal_recall": ev["cal_recall"], "recall": ev["recall"],
+                     "qps": ev["qps"]})
+        log(f"half-bounded {layout}: {rows[-1]}")
+        del b
+        ix.free()
+        torch.cuda.empty_cache()
+    print(json.dumps({"half_bounded": rows, "workload": w["name"], "n": n, "k": k,
+                      "queries": len(w["Q"]), "calibration_queries": CAL_QUERIES}), flush=True)
+
+
+def _chain_sizes(n, leaf, base):
+    out, s = [], n
+    while s - 1 >= leaf:
+        out.append(s)
+        if s == 1:
+            break
+        s = -(-s // base)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -376,6 +429,9 @@ def main():
         args.n = 200_000
     if args.fanout_sweep:
         fanout_sweep(args, cid, dev)
+        return
+    if args.half_bounded:
+        half_bounded(args, cid, dev)
         return
     t0 = time.time()
     w = synth.make_workload(cid, n=args.n, nq=args.nq)

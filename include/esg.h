@@ -60,7 +60,7 @@ extern "C" {
  * bytes [0,512): header
  *   char     magic[8]  = "ESGIDX01"
  *   uint32   version   = 1, header_bytes = 512
- *   int64    n;  int32 d, degree, leaf, fanout, n_depth, c_den, ef_construction, pad
+ *   int64    n;  int32 d, degree, leaf, fanout, n_depth, c_den, ef_construction, layout
  *   uint64   off_ids, off_attr, off_vec, off_adj, off_ep, file_bytes
  *   uint32   crc32c of the sections ids, attr, vec, adj, ep (in that order)
  *   uint32   crc32c of header bytes [0,124)
@@ -78,6 +78,17 @@ extern "C" {
  *                                  no graph
  * c_den is the elastic constant's denominator (c = 1/c_den); the builder
  * writes c_den = fanout and the loader requires c_den >= fanout.
+ * layout 1 (half-bounded index, Section 4.1): the recorded sizes are
+ *   s_0 = n, s_{i+1} = ceil(s_i / fanout) while s_i - 1 >= leaf (K of them);
+ *   n_depth = 2K; depth i < K is the graph of the prefix [0, s_i - 1] and
+ *   depth K + i that of the suffix [n - s_i, n - 1]; adj holds each depth's
+ *   rows for its own positions only, depth after depth (2 sum s_i rows);
+ *   ep is uint32 [n_depth + 1], the entry of depth t at index t + 1.
+ *   A query takes the tightest prefix holding [0, r] (Lemma 4.1: ratio
+ *   >= 1/fanout), or for l > 0 and r = n-1 the tightest suffix holding
+ *   [l, n-1]; a range with both ends inside takes whichever of the two has
+ *   the larger ratio (the prefix on a tie); one that needs a size without a
+ *   graph is scanned.
  * ----------------------------------------------------------------------- */
 
 typedef struct {
@@ -89,7 +100,9 @@ typedef struct {
   int32_t threads;         /* host threads, 0 = all                         */
   int32_t batch_max;       /* largest insertion batch, 0 = default (1024)   */
   int32_t verbose;         /* print progress to stderr                      */
-  int32_t reserved;
+  int32_t layout;          /* 0: segment tree (HBI-2D, Section 4.2); 1: the
+                              half-bounded index (HBI-1D, Section 4.1):
+                              prefix and suffix chains with base = fanout */
 } esg_build_params;
 
 /* Builds the HBI-2D index of Alg. 3 on the host and writes it to out_path.

@@ -10,6 +10,8 @@ Contents and the passage each follows:
 
 * ``read_index``          -- own reader of the documented index file layout.
 * ``select``              -- Alg. 4 subrange selection (Section 4.2).
+* ``select_1d``           -- the half-bounded index's query rule (Section
+                             4.1, Lemma 4.1).
 * ``elastic_factor``      -- Def. 3.1 over the recorded ranges of the tree.
 * ``cd32/cd16/cd8``       -- squared Euclidean distance (Section 2.1) in
                              float32 with the fixed summation order.
@@ -71,7 +73,8 @@ def lib():
 class _Index(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("r", ctypes.c_int32),
                 ("n_depth", ctypes.c_int32), ("leaf", ctypes.c_int32), ("c_den", ctypes.c_int32),
-                ("fanout", ctypes.c_int32),
+                ("fanout", ctypes.c_int32), ("layout", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("row_base", ctypes.c_void_p),
                 ("vec", ctypes.c_void_p), ("vec16", ctypes.c_void_p), ("vec8", ctypes.c_void_p),
                 ("scale8", ctypes.c_void_p), ("adj", ctypes.c_void_p), ("ep", ctypes.c_void_p),
                 ("ext_id", ctypes.c_void_p)]
@@ -84,6 +87,10 @@ def _declare(L):
     L.oracle_elastic_ok.argtypes = [i64, i64, i64, i64, i32]
     L.oracle_elastic_ok.restype = i32
     L.oracle_elastic_factor.argtypes = [i64, i64, i32, i64, i64, vp, vp]
+    L.oracle_select_1d.argtypes = [i64, i64, i32, i64, i64, vp]
+    L.oracle_select_1d.restype = i32
+    L.oracle_chain_graphs.argtypes = [i64, i64, i32]
+    L.oracle_chain_graphs.restype = i64
     L.oracle_elastic_factor.restype = i32
     L.oracle_cd32.argtypes = [vp, vp, i32]
     L.oracle_cd32.restype = f32
@@ -126,9 +133,14 @@ def _p(a: np.ndarray | None):
 class OracleIndex:
     """Arrays of one index in host memory plus the C view the oracle uses."""
 
-    def __init__(self, n, d, degree, leaf, n_depth, c_den, ext_id, attr, vec, adj, ep, fanout=2):
+    def __init__(self, n, d, degree, leaf, n_depth, c_den, ext_id, attr, vec, adj, ep, fanout=2,
+                 layout=0, row_base=None):
         self.n, self.d, self.degree, self.leaf = int(n), int(d), int(degree), int(leaf)
         self.n_depth, self.c_den, self.fanout = int(n_depth), int(c_den), int(fanout)
+        self.layout = int(layout)
+        # row of position p at depth t: adj_flat[(row_base[t] + p) * degree]
+        self.row_base = (np.arange(self.n_depth, dtype=np.int64) * self.n if row_base is None
+                         else np.ascontiguousarray(row_base, dtype=np.int64))
         self.ext_id = np.ascontiguousarray(ext_id, dtype=np.int64)
         self.attr = np.ascontiguousarray(attr, dtype=np.float64)
         self.vec = np.ascontiguousarray(vec, dtype=np.float32)
@@ -140,8 +152,16 @@ class OracleIndex:
         self._c = None
 
     def select(self, lq: int, rq: int):
-        """Alg. 4 on this index's tree (its leaf bound, fanout and c)."""
+        """Alg. 4 on this index's tree (its leaf bound, fanout and c), or the
+        half-bounded index's rule for a chain index."""
+        if self.layout == 1:
+            return select_1d(self.n, self.leaf, int(lq), int(rq), base=self.fanout)
         return select(self.n, self.leaf, int(lq), int(rq), c_den=self.c_den, fanout=self.fanout)
+
+    def rows(self, depth: int):
+        """Adjacency rows of a depth, indexed by position (a view)."""
+        flat = self.adj.reshape(-1, self.degree)
+        return flat[self.row_base[depth]:]
 
     def with_bf16(self):
         self.vec16 = bf16_encode(self.vec)
@@ -158,6 +178,7 @@ class OracleIndex:
             s = _Index()
             s.n, s.d, s.r, s.n_depth = self.n, self.d, self.degree, self.n_depth
             s.leaf, s.c_den, s.fanout = self.leaf, self.c_den, self.fanout
+            s.layout, s.pad_, s.row_base = self.layout, 0, _p(self.row_base)
             s.vec, s.vec16, s.vec8 = _p(self.vec), _p(self.vec16), _p(self.vec8)
             s.scale8, s.adj, s.ep, s.ext_id = _p(self.scale8), _p(self.adj), _p(self.ep), _p(self.ext_id)
             self._c = s
@@ -171,7 +192,7 @@ def read_index(path: str) -> OracleIndex:
         raise ValueError("not an index file")
     version, header_bytes = struct.unpack_from("<II", head, 8)
     n, = struct.unpack_from("<q", head, 16)
-    d, degree, leaf, fanout, n_depth, c_den, efc, _ = struct.unpack_from("<8i", head, 24)
+    d, degree, leaf, fanout, n_depth, c_den, efc, layout = struct.unpack_from("<8i", head, 24)
     off_ids, off_attr, off_vec, off_adj, off_ep, file_bytes = struct.unpack_from("<6Q", head, 56)
     if version != 1 or fanout < 2:
         raise ValueError("unsupported index version/fanout")
@@ -185,9 +206,30 @@ def read_index(path: str) -> OracleIndex:
     ext_id = sect(off_ids, np.int64, n)
     attr = sect(off_attr, np.float64, n)
     vec = sect(off_vec, np.float32, n * d).reshape(n, d)
+    if layout == 1:
+        sizes, starts = chain_levels(n, leaf, fanout)
+        assert len(sizes) == n_depth
+        row_base = np.cumsum([0] + sizes[:-1]) - np.array(starts, np.int64)
+        adj = sect(off_adj, np.uint32, int(sum(sizes)) * degree)
+        ep = sect(off_ep, np.uint32, n_depth + 1)
+        return OracleIndex(n, d, degree, leaf, n_depth, c_den, ext_id, attr, vec, adj, ep, fanout,
+                           layout=1, row_base=row_base)
     adj = sect(off_adj, np.uint32, n_depth * n * degree).reshape(n_depth, n, degree)
     ep = sect(off_ep, np.uint32, node_numbers(fanout, n_depth))
     return OracleIndex(n, d, degree, leaf, n_depth, c_den, ext_id, attr, vec, adj, ep, fanout)
+
+
+def chain_levels(n: int, leaf: int, base: int):
+    """Depths of the half-bounded index: the recorded prefixes [0, s_i - 1]
+    that own a graph (s_0 = n, s_{i+1} = ceil(s_i / base), s_i - 1 >= leaf),
+    then the suffixes [n - s_i, n - 1] of the same sizes.  Returns (sizes,
+    first positions) per depth."""
+    k = int(lib().oracle_chain_graphs(n, leaf, base))
+    sizes, s = [], n
+    for _ in range(k):
+        sizes.append(s)
+        s = -(-s // base)
+    return sizes + sizes, [0] * k + [n - x for x in sizes]
 
 
 def node_numbers(fanout: int, n_depth: int) -> int:
@@ -286,6 +328,17 @@ def select(n: int, leaf: int, lq: int, rq: int, c_den: int = 2, max_parts: int =
         raise ValueError(f"invalid range [{lq},{rq}] for n={n}")
     keys = ("kind", "depth", "heap", "a", "b", "x", "y")
     return [dict(zip(keys, map(int, buf[i]))) for i in range(min(cnt, max_parts))], cnt
+
+
+def select_1d(n: int, leaf: int, lq: int, rq: int, base: int = 2):
+    """The half-bounded index's part for [lq, rq] (one part, as a list of
+    one dict like ``select``) and the count 1."""
+    buf = np.zeros(7, dtype=np.int64)
+    cnt = lib().oracle_select_1d(n, leaf, base, lq, rq, _p(buf))
+    if cnt < 0:
+        raise ValueError(f"invalid range [{lq},{rq}] for n={n}")
+    keys = ("kind", "depth", "heap", "a", "b", "x", "y")
+    return [dict(zip(keys, map(int, buf)))], 1
 
 
 def elastic_factor(n: int, leaf: int, l: int, r: int, fanout: int = 2):

@@ -11,6 +11,10 @@
  *   oracle_select        Alg. 4 (Query-2D-Index) recursion, Section 4.2, with
  *                        the elastic test of Def. 3.1 at c = 1/c_den, for a
  *                        segment tree of fanout f (Section 4.2, Extensions).
+ *   oracle_select_1d     the query rule of the half-bounded index (Section
+ *                        4.1, Lemma 4.1): the tightest recorded prefix
+ *                        [0, s-1] holding [0, r] (or suffix holding [l, N-1]),
+ *                        recorded sizes s_0 = N, s_{i+1} = ceil(s_i / B).
  *   oracle_elastic_ok    Def. 3.1 test |[x,y]| / |[a,b]| >= c, in integers.
  *   oracle_cd32/16/8     squared Euclidean distance (Section 2.1) in float32
  *                        with a fixed summation order, see below.
@@ -79,12 +83,15 @@ typedef struct {
   int32_t n_depth;        /* tree depths that hold at least one graph */
   int32_t leaf;           /* leaf bound: node [a,b] has a graph iff b-a >= leaf */
   int32_t c_den;          /* elastic constant c = 1/c_den */
-  int32_t fanout;         /* children per tree node */
+  int32_t fanout;         /* children per tree node (chain base B of the 1-D index) */
+  int32_t layout;         /* 0: segment tree (HBI-2D); 1: prefix and suffix chains (HBI-1D) */
+  int32_t pad_;
+  const int64_t* row_base;/* [n_depth]: row of position p in depth t is adj + (row_base[t] + p) r */
   const float* vec;       /* [n][d] float32 in position order */
   const uint16_t* vec16;  /* [n][d] bfloat16 bit patterns, or NULL */
   const uint8_t* vec8;    /* [n][d] fp8 e4m3 codes, or NULL */
   const float* scale8;    /* [n] per-vector fp8 scale, or NULL */
-  const uint32_t* adj;    /* [n_depth][n][r] neighbour positions, NO_NODE pad */
+  const uint32_t* adj;    /* neighbour positions, NO_NODE pad (rows addressed by row_base) */
   const uint32_t* ep;     /* entry point by node number (root = 1) */
   const int64_t* ext_id;  /* [n] external id of each position */
 } oracle_index;
@@ -154,6 +161,62 @@ int32_t oracle_select(int64_t n, int64_t leaf, int32_t c_den, int32_t fanout, in
   select_ctx s = {parts, max_parts, 0, leaf, c_den, fanout};
   query2d(&s, 0, n - 1, 0, 1, lq, rq);
   return s.n_parts;
+}
+
+/* Half-bounded index (Section 4.1): recorded prefixes [0, s_i - 1] with
+ * s_0 = n, s_{i+1} = ceil(s_i / B) (the ranges [1, N/B^i] of Alg. 2 with
+ * the division rounded up, down to one point), and the mirrored suffixes
+ * [n - s_i, n - 1].  Depth i holds prefix i, depth K + i suffix i, where K
+ * is the number of prefixes that own a graph (s_i - 1 >= leaf).  A query
+ * [l, r] takes the tightest recorded prefix holding [0, r] -- ratio
+ * (r+1)/s_i >= 1/B (Lemma 4.1) -- or, when l > 0 and r = n-1, the tightest
+ * suffix holding [l, n-1].  A range with both ends inside (not
+ * half-bounded; outside the index's own scope) takes whichever of the two
+ * covers it with the larger ratio (ties: the prefix).  A chosen prefix or
+ * suffix without a graph (s - 1 < leaf) is a linear scan of [l, r].
+ * Writes one part (kind, depth, node number = depth + 1, a, b, l, r);
+ * returns 1, or OR_EINVAL for a bad range. */
+int64_t oracle_chain_graphs(int64_t n, int64_t leaf, int32_t base) {
+  int64_t k = 0;
+  for (int64_t s = n; s - 1 >= leaf; s = (s + base - 1) / base) {
+    k++;
+    if (s == 1) break;
+  }
+  return k;
+}
+
+int32_t oracle_select_1d(int64_t n, int64_t leaf, int32_t base, int64_t lq, int64_t rq,
+                         int64_t* part) {
+  if (n <= 0 || leaf < 0 || base < 2 || lq < 0 || rq >= n || lq > rq) return OR_EINVAL;
+  int64_t K = oracle_chain_graphs(n, leaf, base);
+  int64_t w = rq - lq + 1;
+  /* tightest prefix holding [0, rq] and tightest suffix holding [lq, n-1] */
+  int64_t sp = n, ip = 0, ss = n, is = 0;
+  while (1) {
+    int64_t nx = (sp + base - 1) / base;
+    if (nx == sp || nx < rq + 1) break;
+    sp = nx; ip++;
+  }
+  while (1) {
+    int64_t nx = (ss + base - 1) / base;
+    if (nx == ss || nx < n - lq) break;
+    ss = nx; is++;
+  }
+  int use_prefix;
+  if (lq == 0) use_prefix = 1;
+  else if (rq == n - 1) use_prefix = 0;
+  else use_prefix = ss >= sp;   /* w/sp >= w/ss: the prefix's ratio is at least as large */
+  int64_t size = use_prefix ? sp : ss, idx = use_prefix ? ip : is;
+  int64_t a = use_prefix ? 0 : n - ss, b = use_prefix ? sp - 1 : n - 1;
+  (void)w;
+  if (size - 1 < leaf) {        /* no graph at this size: scan the query range */
+    part[0] = KIND_SCAN; part[1] = -1; part[2] = 0;
+  } else {
+    int64_t depth = use_prefix ? idx : K + idx;
+    part[0] = KIND_GRAPH; part[1] = depth; part[2] = depth + 1;
+  }
+  part[3] = a; part[4] = b; part[5] = lq; part[6] = rq;
+  return 1;
 }
 
 /* Elastic factor e(R,[l,r]) of Def. 3.1 over the set R of all graph nodes
@@ -400,11 +463,13 @@ int32_t oracle_search_part_sw(const oracle_index* ix, int32_t depth, int64_t hea
   if (m < 1 || cap_p < 1 || depth < 0 || depth >= ix->n_depth) return OR_EINVAL;
   if (!(0 <= a && a <= x && x <= y && y <= b && b < ix->n)) return OR_EINVAL;
   int64_t n_heap = 1, level = 1;                  /* node numbers of depths < n_depth */
-  for (int32_t t = 0; t < ix->n_depth; t++) { n_heap += level; level *= ix->fanout; }
+  if (ix->layout == 1) n_heap = ix->n_depth + 1;  /* chains: node number = depth + 1 */
+  else
+    for (int32_t t = 0; t < ix->n_depth; t++) { n_heap += level; level *= ix->fanout; }
   if (heap < 1 || heap >= n_heap) return OR_EINVAL;
   uint32_t ep = ix->ep[heap];
   if (ep == NO_NODE || (int64_t)ep < a || (int64_t)ep > b) return OR_EGRAPH;
-  const uint32_t* rows = ix->adj + (int64_t)depth * ix->n * ix->r;
+  const uint32_t* rows = ix->adj + ix->row_base[depth] * ix->r;
 
   int64_t span = b - a + 1;
   uint8_t* seen = (uint8_t*)calloc((size_t)span, 1); /* visited flags of [a,b] */
@@ -531,7 +596,10 @@ int32_t oracle_query_sw(const oracle_index* ix, const float* q, int64_t lq, int6
   if (stats) memset(stats, 0, sizeof(int64_t) * 8);
   if (k < 1 || ef < k) return OR_EINVAL;
   int64_t parts[MAX_PARTS * 7];
-  int32_t np = oracle_select(ix->n, ix->leaf, ix->c_den, ix->fanout, lq, rq, parts, MAX_PARTS);
+  int32_t np = ix->layout == 1
+                   ? oracle_select_1d(ix->n, ix->leaf, ix->fanout, lq, rq, parts)
+                   : oracle_select(ix->n, ix->leaf, ix->c_den, ix->fanout, lq, rq, parts,
+                                   MAX_PARTS);
   if (np < 0) return np;
   if (np > MAX_PARTS) return OR_EINVAL;
 

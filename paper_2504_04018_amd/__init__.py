@@ -40,7 +40,7 @@ class BuildParams(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int32), ("leaf", ctypes.c_int32),
                 ("ef_construction", ctypes.c_int32), ("fanout", ctypes.c_int32),
                 ("threads", ctypes.c_int32), ("batch_max", ctypes.c_int32),
-                ("verbose", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("verbose", ctypes.c_int32), ("layout", ctypes.c_int32)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -132,14 +132,17 @@ def _check(status: int, what: str):
 
 def build_index(X: np.ndarray, attr: np.ndarray, path: str, degree: int = 16, leaf: int = 1024,
                 ef_construction: int = 200, threads: int = 0, batch_max: int = 0,
-                verbose: bool = False, fanout: int = 2) -> None:
-    """esg_build_index: host build of the HBI-2D index file (Alg. 3) with a
-    segment tree of the given fanout (elastic constant 1/fanout)."""
+                verbose: bool = False, fanout: int = 2, layout: str = "tree") -> None:
+    """esg_build_index: host build of the index file -- layout "tree": the
+    HBI-2D segment tree (Alg. 3) of the given fanout (elastic constant
+    1/fanout); layout "chain": the half-bounded HBI-1D index (Alg. 2),
+    prefix and suffix graphs of sizes N, ceil(N/B), ... with B = fanout."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     attr = np.ascontiguousarray(attr, dtype=np.float64)
     if X.ndim != 2 or attr.shape != (X.shape[0],):
         raise ValueError("X must be [n,d] and attr [n]")
-    p = BuildParams(degree, leaf, ef_construction, fanout, threads, batch_max, int(verbose), 0)
+    p = BuildParams(degree, leaf, ef_construction, fanout, threads, batch_max, int(verbose),
+                    {"tree": 0, "chain": 1}[layout])
     st = lib().esg_build_index(X.ctypes.data, attr.ctypes.data, X.shape[0], X.shape[1],
                                ctypes.byref(p), path.encode())
     _check(st, "esg_build_index")

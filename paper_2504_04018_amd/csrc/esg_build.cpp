@@ -361,6 +361,133 @@ bool pad_to(FILE* f, uint64_t off) {
   return true;
 }
 
+// Writes the index file (layout documented in esg.h).
+int32_t write_index(const char* out_path, int64_t n, int32_t d, const esg_build_params& P,
+                    int fanout, int n_depth, int layout, const int64_t* ids, const double* attr,
+                    const float* X, const std::vector<uint32_t>& adj,
+                    const std::vector<uint32_t>& ep) {
+  const uint64_t adj_bytes = (uint64_t)adj.size() * 4, ep_bytes = (uint64_t)ep.size() * 4;
+  esg::FileHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, esg::kMagic, 8);
+  h.version = esg::kVersion;
+  h.header_bytes = esg::kHeaderBytes;
+  h.n = n;
+  h.d = d;
+  h.degree = P.degree;
+  h.leaf = P.leaf;
+  h.fanout = fanout;
+  h.n_depth = n_depth;
+  h.c_den = fanout;   // elastic constant c = 1/fanout (Lemma 4.3; Lemma 4.1 with base B)
+  h.layout = layout;
+  h.ef_construction = P.ef_construction;
+  h.off_ids = esg::align_up(esg::kHeaderBytes);
+  h.off_attr = esg::align_up(h.off_ids + esg::bytes_ids(n));
+  h.off_vec = esg::align_up(h.off_attr + esg::bytes_attr(n));
+  h.off_adj = esg::align_up(h.off_vec + esg::bytes_vec(n, d));
+  h.off_ep = esg::align_up(h.off_adj + adj_bytes);
+  h.file_bytes = h.off_ep + ep_bytes;
+  const esg::Crc32c& crc = esg::crc32c();
+  h.crc_sections[0] = crc.update(0, ids, esg::bytes_ids(n));
+  h.crc_sections[1] = crc.update(0, attr, esg::bytes_attr(n));
+  h.crc_sections[2] = crc.update(0, X, esg::bytes_vec(n, d));
+  h.crc_sections[3] = crc.update(0, adj.data(), adj_bytes);
+  h.crc_sections[4] = crc.update(0, ep.data(), ep_bytes);
+  h.crc_header = crc.update(0, &h, offsetof(esg::FileHeader, crc_header));
+
+  FILE* f = fopen(out_path, "wb");
+  if (!f) return ESG_EIO;
+  bool ok = write_all(f, &h, sizeof(h)) && pad_to(f, h.off_ids) &&
+            write_all(f, ids, esg::bytes_ids(n)) && pad_to(f, h.off_attr) &&
+            write_all(f, attr, esg::bytes_attr(n)) && pad_to(f, h.off_vec) &&
+            write_all(f, X, esg::bytes_vec(n, d)) && pad_to(f, h.off_adj) &&
+            write_all(f, adj.data(), adj_bytes) &&
+            pad_to(f, h.off_ep) && write_all(f, ep.data(), ep_bytes);
+  ok = (fclose(f) == 0) && ok;
+  return ok ? ESG_OK : ESG_EIO;
+}
+
+// Half-bounded index (Section 4.1, Alg. 2): the points are inserted in
+// position order into one graph, and the graph is recorded each time the
+// inserted prefix reaches a recorded size s_i (smallest first); the suffix
+// chain does the same in decreasing position order (built on the mirrored
+// positions p -> n-1-p and mapped back).  Each recorded graph gets its
+// medoid entry and the reachability repair before the insertion goes on.
+template <typename Snapshot>
+void build_chain(Builder& B, const std::vector<int64_t>& sizes, std::vector<uint32_t>& W,
+                 std::vector<uint32_t>& eps, Snapshot snapshot) {
+  const int R = B.R;
+  const size_t k = sizes.size();
+  eps.assign(k, ESG_NO_NODE);
+  std::fill(W.begin(), W.end(), ESG_NO_NODE);
+  B.adj = W.data();
+  int64_t done = 0;                     // positions [0, done) inserted
+  for (size_t j = k; j-- > 0;) {
+    const int64_t s = sizes[j];
+    if (done == 0) {
+      if (s > 1) B.insert_range(W.data(), 0, 1, s - 1, true);
+    } else if (s > done) {
+      B.insert_range(W.data(), 0, done, s - 1, true);
+    }
+    done = s;
+    const uint32_t e = B.medoid(0, s - 1);
+    B.repair(0, 0, s - 1, e);
+    eps[j] = e;
+    snapshot(j, s);                     // record the graph of [0, s - 1] now
+    if (B.verbose)
+      fprintf(stderr, "[esg_build] chain prefix of %lld points recorded\n", (long long)s);
+    (void)R;
+  }
+}
+
+int32_t build_chains(const float* X, const std::vector<int64_t>& order,
+                     const std::vector<double>& sorted_attr, int64_t n, int32_t d,
+                     const esg_build_params& P, int fanout, const char* out_path) {
+  const std::vector<int64_t> sizes = esg::chain_sizes(n, P.leaf, fanout);
+  const size_t k = sizes.size();
+  if (k == 0 || 2 * k > 40) return ESG_ERANGE;
+  const int R = P.degree;
+  Builder B;
+  B.n = n;
+  B.d = d;
+  B.R = R;
+  B.leaf = P.leaf;
+  B.efc = P.ef_construction;
+  B.batch_max = P.batch_max > 0 ? P.batch_max : 1024;
+  B.n_depth = 1;
+  B.verbose = P.verbose;
+  B.fanout = fanout;
+  std::vector<uint32_t> W((size_t)n * R), eps_p, eps_s;
+  const std::vector<int64_t> row_base = esg::chain_row_base(n, sizes);
+  std::vector<uint32_t> adj((size_t)esg::chain_rows(sizes) * R, ESG_NO_NODE);
+  // prefixes
+  B.X = X;
+  build_chain(B, sizes, W, eps_p, [&](size_t i, int64_t s) {
+    std::memcpy(&adj[(size_t)row_base[i] * R], W.data(), sizeof(uint32_t) * R * (size_t)s);
+  });
+  // suffixes on the mirrored positions p -> n-1-p
+  std::vector<float> Xr((size_t)n * d);
+  for (int64_t p = 0; p < n; p++)
+    std::memcpy(&Xr[(size_t)p * d], X + (size_t)(n - 1 - p) * d, sizeof(float) * d);
+  B.X = Xr.data();
+  build_chain(B, sizes, W, eps_s, [&](size_t i, int64_t s) {
+    const size_t t = k + i;
+    for (int64_t p = n - s; p < n; p++) {
+      const uint32_t* src = &W[(size_t)(n - 1 - p) * R];
+      uint32_t* dst = &adj[(size_t)(row_base[t] + p) * R];
+      for (int j = 0; j < R; j++)
+        dst[j] = src[j] == ESG_NO_NODE ? ESG_NO_NODE : (uint32_t)(n - 1 - (int64_t)src[j]);
+    }
+  });
+  std::vector<uint32_t> ep(2 * k + 1, ESG_NO_NODE);   // node number = depth + 1
+  for (size_t i = 0; i < k; i++) {
+    ep[1 + i] = eps_p[i];
+    ep[1 + k + i] = (uint32_t)(n - 1 - (int64_t)eps_s[i]);
+  }
+  return write_index(out_path, n, d, P, fanout, (int)(2 * k), 1, order.data(), sorted_attr.data(), X,
+                     adj, ep);
+}
+
 }  // namespace
 
 extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_t n, int32_t d,
@@ -369,7 +496,7 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
     return ESG_EINVAL;
   const esg_build_params& P = *params;
   if (P.degree < 1 || P.degree > ESG_DEGREE_MAX || P.leaf < 1 || P.ef_construction < 1 ||
-      P.fanout < 0 || P.fanout == 1)
+      P.fanout < 0 || P.fanout == 1 || P.layout < 0 || P.layout > 1)
     return ESG_EINVAL;
   const int fanout = P.fanout == 0 ? 2 : P.fanout;
   if (fanout > ESG_FANOUT_MAX) return ESG_EUNSUPPORTED;
@@ -392,6 +519,8 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
       std::memcpy(&X[(size_t)p * d], vecs + (size_t)order[(size_t)p] * d, sizeof(float) * d);
     }
 
+    if (P.layout == 1)
+      return build_chains(X.data(), order, sorted_attr, n, d, P, fanout, out_path);
     std::vector<NodeRef> nodes;
     collect(0, n - 1, 0, 1, P.leaf, fanout, nodes);
     int n_depth = 0;
@@ -438,44 +567,8 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
                 t, level.size(), (long long)repaired);
     }
 
-    // Write the file.
-    esg::FileHeader h;
-    std::memset(&h, 0, sizeof(h));
-    std::memcpy(h.magic, esg::kMagic, 8);
-    h.version = esg::kVersion;
-    h.header_bytes = esg::kHeaderBytes;
-    h.n = n;
-    h.d = d;
-    h.degree = P.degree;
-    h.leaf = P.leaf;
-    h.fanout = fanout;
-    h.n_depth = n_depth;
-    h.c_den = fanout;   // elastic constant c = 1/fanout (Lemma 4.3)
-    h.ef_construction = P.ef_construction;
-    h.off_ids = esg::align_up(esg::kHeaderBytes);
-    h.off_attr = esg::align_up(h.off_ids + esg::bytes_ids(n));
-    h.off_vec = esg::align_up(h.off_attr + esg::bytes_attr(n));
-    h.off_adj = esg::align_up(h.off_vec + esg::bytes_vec(n, d));
-    h.off_ep = esg::align_up(h.off_adj + esg::bytes_adj(n, n_depth, P.degree));
-    h.file_bytes = h.off_ep + esg::bytes_ep(n_depth, fanout);
-    const esg::Crc32c& crc = esg::crc32c();
-    h.crc_sections[0] = crc.update(0, order.data(), esg::bytes_ids(n));
-    h.crc_sections[1] = crc.update(0, sorted_attr.data(), esg::bytes_attr(n));
-    h.crc_sections[2] = crc.update(0, X.data(), esg::bytes_vec(n, d));
-    h.crc_sections[3] = crc.update(0, adj.data(), esg::bytes_adj(n, n_depth, P.degree));
-    h.crc_sections[4] = crc.update(0, ep.data(), esg::bytes_ep(n_depth, fanout));
-    h.crc_header = crc.update(0, &h, offsetof(esg::FileHeader, crc_header));
-
-    FILE* f = fopen(out_path, "wb");
-    if (!f) return ESG_EIO;
-    bool ok = write_all(f, &h, sizeof(h)) && pad_to(f, h.off_ids) &&
-              write_all(f, order.data(), esg::bytes_ids(n)) && pad_to(f, h.off_attr) &&
-              write_all(f, sorted_attr.data(), esg::bytes_attr(n)) && pad_to(f, h.off_vec) &&
-              write_all(f, X.data(), esg::bytes_vec(n, d)) && pad_to(f, h.off_adj) &&
-              write_all(f, adj.data(), esg::bytes_adj(n, n_depth, P.degree)) &&
-              pad_to(f, h.off_ep) && write_all(f, ep.data(), esg::bytes_ep(n_depth, fanout));
-    ok = (fclose(f) == 0) && ok;
-    return ok ? ESG_OK : ESG_EIO;
+    return write_index(out_path, n, d, P, fanout, n_depth, 0, order.data(), sorted_attr.data(),
+                       X.data(), adj, ep);
   } catch (const std::bad_alloc&) {
     return ESG_ENOMEM;
   } catch (...) {

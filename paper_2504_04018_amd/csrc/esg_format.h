@@ -5,6 +5,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
+#include <vector>
 
 namespace esg {
 
@@ -19,7 +20,7 @@ struct FileHeader {
   uint32_t version;
   uint32_t header_bytes;
   int64_t n;
-  int32_t d, degree, leaf, fanout, n_depth, c_den, ef_construction, pad;
+  int32_t d, degree, leaf, fanout, n_depth, c_den, ef_construction, layout;
   uint64_t off_ids, off_attr, off_vec, off_adj, off_ep, file_bytes;
   uint32_t crc_sections[5];
   uint32_t crc_header;  // crc32c of bytes [0, offsetof(crc_header))
@@ -52,6 +53,38 @@ inline uint64_t ep_count(int32_t depth, int32_t fanout) {
   return c;
 }
 inline uint64_t bytes_ep(int32_t depth, int32_t fanout) { return ep_count(depth, fanout) * 4; }
+
+// Chain layout (the half-bounded index): the recorded prefix sizes that own
+// a graph, s_0 = n, s_{i+1} = ceil(s_i / base), while s_i - 1 >= leaf.
+// Depth i < K holds prefix [0, s_i - 1]; depth K + i the suffix
+// [n - s_i, n - 1].  Rows are stored depth after depth, each depth's rows
+// for its own positions only.
+inline std::vector<int64_t> chain_sizes(int64_t n, int32_t leaf, int32_t base) {
+  std::vector<int64_t> out;
+  for (int64_t s = n; s - 1 >= leaf; s = (s + base - 1) / base) {
+    out.push_back(s);
+    if (s == 1) break;
+  }
+  return out;
+}
+// Row offset of position p at depth t is row_base[t] + p.
+inline std::vector<int64_t> chain_row_base(int64_t n, const std::vector<int64_t>& sizes) {
+  const size_t k = sizes.size();
+  std::vector<int64_t> base(2 * k);
+  int64_t off = 0;
+  for (size_t t = 0; t < 2 * k; t++) {
+    const int64_t sz = sizes[t % k];
+    const int64_t start = t < k ? 0 : n - sz;
+    base[t] = off - start;
+    off += sz;
+  }
+  return base;
+}
+inline int64_t chain_rows(const std::vector<int64_t>& sizes) {
+  int64_t r = 0;
+  for (int64_t s : sizes) r += 2 * s;
+  return r;
+}
 
 // Software CRC-32C (Castagnoli, reflected polynomial 0x82F63B78), eight
 // bytes per step with slicing tables.

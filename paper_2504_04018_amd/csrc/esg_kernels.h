@@ -36,13 +36,14 @@ struct SearchArgs {
   const uint16_t* vec16;  // [n][dp] bfloat16 bits or null
   const uint8_t* vec8;    // [n][dp] fp8 e4m3 codes or null
   const float* scale8;    // [n] fp8 scales or null
-  const uint32_t* adj;    // [n_depth][n][R]
+  const uint32_t* adj;    // rows of every depth, addressed through row_base
   const uint32_t* ep;     // [2^n_depth]
   const int64_t* ext_id;  // [n]
   int64_t n;
   int32_t d, dp, R, leaf, n_depth, c_den;
-  int32_t fanout;         // children per tree node
-  int32_t pad0_;
+  int32_t fanout;         // children per tree node (the chains' base in layout 1)
+  int32_t layout;         // 0: segment tree; 1: prefix and suffix chains (half-bounded index)
+  const int64_t* row_base;// [n_depth]: row of position p at depth t is adj + (row_base[t] + p) R
   // batch
   const float* queries;   // [nq][d]
   const int64_t* l;

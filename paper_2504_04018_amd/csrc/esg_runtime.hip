@@ -59,7 +59,8 @@ hipError_t dev_alloc(void** p, size_t bytes) {
 struct esg_index {
   int device = 0;
   int64_t n = 0;
-  int32_t d = 0, dp = 0, R = 0, leaf = 0, n_depth = 0, c_den = 2, fanout = 2;
+  int32_t d = 0, dp = 0, R = 0, leaf = 0, n_depth = 0, c_den = 2, fanout = 2, layout = 0;
+  int64_t* row_base = nullptr;  // [n_depth] device: row of position p at depth t = row_base[t] + p
   float* vec = nullptr;
   uint16_t* vec16 = nullptr;
   uint8_t* vec8 = nullptr;
@@ -290,6 +291,25 @@ bool read_exact(FILE* f, uint64_t off, void* dst, uint64_t bytes) {
   return true;
 }
 
+// Chain layout: every recorded prefix or suffix graph has its entry and all
+// neighbours of its rows inside its own range.
+bool chains_are_consistent(int64_t n, const std::vector<int64_t>& sizes, int32_t R,
+                           const std::vector<int64_t>& row_base, const uint32_t* adj,
+                           const uint32_t* ep) {
+  const size_t k = sizes.size();
+  for (size_t t = 0; t < 2 * k; t++) {
+    const int64_t sz = sizes[t % k], a = t < k ? 0 : n - sz, b = a + sz - 1;
+    const uint32_t e = ep[t + 1];
+    if (e == ESG_NO_NODE || (int64_t)e < a || (int64_t)e > b) return false;
+    for (int64_t p = a; p <= b; p++)
+      for (int32_t j = 0; j < R; j++) {
+        const uint32_t v = adj[(size_t)(row_base[t] + p) * R + j];
+        if (v != ESG_NO_NODE && ((int64_t)v < a || (int64_t)v > b)) return false;
+      }
+  }
+  return true;
+}
+
 bool tree_is_consistent(int64_t n, int32_t leaf, int32_t fanout, int32_t n_depth, int32_t R,
                         const uint32_t* adj, const uint32_t* ep) {
   struct Node {
@@ -345,12 +365,26 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
   if (crc.update(0, &h, offsetof(esg::FileHeader, crc_header)) != h.crc_header) return ESG_EFORMAT;
   if (h.n <= 0 || h.n >= (int64_t)ESG_NO_NODE || h.d <= 0 || h.d > 65536 || h.degree < 1 ||
       h.degree > ESG_DEGREE_MAX || h.leaf < 1 || h.fanout < 2 || h.fanout > ESG_FANOUT_MAX ||
-      h.n_depth < 0 || h.n_depth > 40 || h.c_den < h.fanout ||
-      esg::ep_count(h.n_depth, h.fanout) == 0)
+      h.n_depth < 0 || h.n_depth > 40 || h.c_den < h.fanout || h.layout < 0 || h.layout > 1 ||
+      (h.layout == 0 && esg::ep_count(h.n_depth, h.fanout) == 0))
     return ESG_EFORMAT;   // c = 1/c_den <= 1/fanout keeps Alg. 4 at two parts at most
+  // rows per depth: the tree's depths cover all n positions; the chains'
+  // depths only their own prefix or suffix
+  std::vector<int64_t> row_base((size_t)h.n_depth);
+  uint64_t adj_rows = (uint64_t)h.n_depth * (uint64_t)h.n, ep_slots = 0;
+  std::vector<int64_t> chain;
+  if (h.layout == 1) {
+    chain = esg::chain_sizes(h.n, h.leaf, h.fanout);
+    if ((int64_t)h.n_depth != 2 * (int64_t)chain.size()) return ESG_EFORMAT;
+    row_base = esg::chain_row_base(h.n, chain);
+    adj_rows = (uint64_t)esg::chain_rows(chain);
+    ep_slots = (uint64_t)h.n_depth + 1;
+  } else {
+    for (int32_t t = 0; t < h.n_depth; t++) row_base[(size_t)t] = (int64_t)t * h.n;
+    ep_slots = esg::ep_count(h.n_depth, h.fanout);
+  }
   const uint64_t sizes[5] = {esg::bytes_ids(h.n), esg::bytes_attr(h.n), esg::bytes_vec(h.n, h.d),
-                             esg::bytes_adj(h.n, h.n_depth, h.degree),
-                             esg::bytes_ep(h.n_depth, h.fanout)};
+                             adj_rows * (uint64_t)h.degree * 4, ep_slots * 4};
   const uint64_t offs[5] = {h.off_ids, h.off_attr, h.off_vec, h.off_adj, h.off_ep};
   uint64_t prev_end = esg::kHeaderBytes;
   for (int s = 0; s < 5; s++) {
@@ -369,8 +403,8 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
 
   std::vector<int64_t> ids((size_t)h.n);
   std::vector<float> vec((size_t)h.n * (size_t)h.d);
-  std::vector<uint32_t> adj((size_t)h.n_depth * (size_t)h.n * (size_t)h.degree);
-  std::vector<uint32_t> ep((size_t)esg::ep_count(h.n_depth, h.fanout));
+  std::vector<uint32_t> adj((size_t)adj_rows * (size_t)h.degree);
+  std::vector<uint32_t> ep((size_t)ep_slots);
   std::vector<double> attr((size_t)h.n);
   void* dsts[5] = {ids.data(), attr.data(), vec.data(), adj.data(), ep.data()};
   for (int s = 0; s < 5; s++) {
@@ -379,7 +413,9 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
   }
   // Structural checks the kernels rely on: every graph node [a,b] of the
   // tree has its entry point and all neighbours of its rows inside [a,b].
-  if (!tree_is_consistent(h.n, h.leaf, h.fanout, h.n_depth, h.degree, adj.data(), ep.data()))
+  if (h.layout == 1 ? !chains_are_consistent(h.n, chain, h.degree, row_base, adj.data(), ep.data())
+                    : !tree_is_consistent(h.n, h.leaf, h.fanout, h.n_depth, h.degree, adj.data(),
+                                          ep.data()))
     return ESG_EFORMAT;
 
   int ndev = 0;
@@ -401,6 +437,7 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
   ix->n_depth = h.n_depth;
   ix->c_den = h.c_den;
   ix->fanout = h.fanout;
+  ix->layout = h.layout;
   ix->kt = kt;
   if (hipDeviceGetAttribute(&ix->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device) !=
       hipSuccess) {
@@ -422,6 +459,7 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
   A((void**)&ix->spill, spill_bytes);
   A((void**)&ix->counter, 256);
   A((void**)&ix->mlp_pack, sizeof(float) * esgk::kMlpParams);
+  A((void**)&ix->row_base, std::max<size_t>(8, row_base.size() * 8));
   if (st != ESG_OK) {
     ix->release();
     delete ix;
@@ -433,6 +471,8 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
             (adj.empty() ||
              hipMemcpy(ix->adj, adj.data(), adj.size() * 4, hipMemcpyHostToDevice) == hipSuccess) &&
             hipMemcpy(ix->ep, ep.data(), ep.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+            (row_base.empty() || hipMemcpy(ix->row_base, row_base.data(), row_base.size() * 8,
+                                           hipMemcpyHostToDevice) == hipSuccess) &&
             hipMemcpy(ix->ext_id, ids.data(), ids.size() * 8, hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemset(ix->counter, 0, 256) == hipSuccess &&
@@ -899,6 +939,8 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   a.n_depth = idx->n_depth;
   a.c_den = idx->c_den;
   a.fanout = idx->fanout;
+  a.layout = idx->layout;
+  a.row_base = idx->row_base;
   a.queries = queries;
   a.l = l;
   a.r = r;

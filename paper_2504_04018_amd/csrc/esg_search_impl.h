@@ -489,13 +489,65 @@ __device__ __forceinline__ Part to_part(const Desc& it, int64_t leaf) {
           (uint32_t)it.x, (uint32_t)it.y};
 }
 
+// Half-bounded index (Section 4.1): the tightest recorded prefix
+// [0, s - 1] holding [0, rq] (ratio >= 1/B by Lemma 4.1), or for lq > 0 and
+// rq = n - 1 the tightest suffix [n - s, n - 1] holding [lq, n - 1]; a
+// range with both ends inside takes whichever covers it with the larger
+// ratio (the prefix on a tie).  Sizes s_0 = n, s_{i+1} = ceil(s_i / B);
+// depth i (prefix) or K + i (suffix) for the K sizes with a graph, node
+// number depth + 1; a size without a graph (s - 1 < leaf) is scanned.
+__device__ __forceinline__ Part select_chain(int64_t n, int64_t leaf, int32_t B, int64_t lq,
+                                             int64_t rq) {
+  int64_t sp = n, ip = 0, ss = n, is = 0, K = 0;
+  for (int64_t s = n; s - 1 >= leaf; s = (s + B - 1) / B) {
+    K++;
+    if (s == 1) break;
+  }
+  for (;;) {
+    const int64_t nx = (sp + B - 1) / B;
+    if (nx == sp || nx < rq + 1) break;
+    sp = nx;
+    ip++;
+  }
+  for (;;) {
+    const int64_t nx = (ss + B - 1) / B;
+    if (nx == ss || nx < n - lq) break;
+    ss = nx;
+    is++;
+  }
+  const bool pre = lq == 0 ? true : (rq == n - 1 ? false : ss >= sp);
+  const int64_t size = pre ? sp : ss;
+  Part p;
+  p.a = (uint32_t)(pre ? 0 : n - ss);
+  p.b = (uint32_t)(pre ? sp - 1 : n - 1);
+  p.x = (uint32_t)lq;
+  p.y = (uint32_t)rq;
+  if (size - 1 < leaf) {
+    p.kind = 2;
+    p.depth = -1;
+    p.heap = 0;
+  } else {
+    p.kind = 1;
+    p.depth = (int32_t)(pre ? ip : K + is);
+    p.heap = p.depth + 1;
+  }
+  return p;
+}
+
 // Alg. 4: at most two parts (Lemma 4.2 at fanout 2, Lemma 4.3 at fanout f
 // with c = 1/f).  Returns the count (or -1 if the descent would emit more:
 // never when c_den >= fanout, which the loader enforces) and part `which`
 // (0 or 1) in `out`.  The search recomputes the descent for each part (a few
-// scalar steps) so that no part record has to be kept in memory.
-__device__ __forceinline__ int select_parts(int64_t n, int64_t leaf, int32_t c_den, int32_t fanout,
-                                            int64_t lq, int64_t rq, int which, Part& out) {
+// scalar steps) so that no part record has to be kept in memory.  A chain
+// index gives one part (select_chain).
+__device__ __forceinline__ int select_parts(const SearchArgs& A, int64_t lq, int64_t rq, int which,
+                                            Part& out) {
+  const int64_t n = A.n, leaf = A.leaf;
+  const int32_t c_den = A.c_den, fanout = A.fanout;
+  if (A.layout == 1) {
+    out = select_chain(n, leaf, fanout, lq, rq);
+    return 1;
+  }
   Desc it = {0, n - 1, lq, rq, 1, 0}, right = it, dummy = it;
   bool split = false, s2 = false;
   if (!descend(it, leaf, c_den, fanout, true, right, split)) return -1;

@@ -138,7 +138,7 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
   list_clear(P);
   list_clear(Q);
   visited_reset(A, V, pt.a, pt.b, lane);
-  const uint32_t* rows = A.adj + (size_t)pt.depth * (size_t)A.n * (size_t)A.R;
+  const uint32_t* rows = A.adj + A.row_base[pt.depth] * (int64_t)A.R;
   const uint32_t ep = A.ep[pt.heap];
 
   // The entry's adjacency row is requested together with its vector, so the
@@ -369,7 +369,7 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
   const int64_t lq = A.l[qi], rq = A.r[qi];
   const bool valid = lq >= 0 && rq < A.n && lq <= rq;
   Part pt{};
-  const int np = valid ? select_parts(A.n, A.leaf, A.c_den, A.fanout, lq, rq, 0, pt) : 0;
+  const int np = valid ? select_parts(A, lq, rq, 0, pt) : 0;
   if (!valid || np < 0) {
     for (int i = lane; i < k; i += kWave) {
       ids[i] = -1;
@@ -391,7 +391,7 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
   // One copy of the part code (not unrolled: half the instruction footprint).
 #pragma nounroll
   for (int p = 0; p < np; p++) {
-    if (p == 1) select_parts(A.n, A.leaf, A.c_den, A.fanout, lq, rq, 1, pt);
+    if (p == 1) select_parts(A, lq, rq, 1, pt);
     uint64_t Qp[E];
     PartStats st{0, 0};
     const uint64_t t_start = A.trace ? __builtin_amdgcn_s_memrealtime() : 0;

@@ -30,7 +30,8 @@ import math
 
 import numpy as np
 
-__all__ = ["Workload", "WORKLOADS", "make_workload", "fixed_width_ranges", "sha256_of"]
+__all__ = ["Workload", "WORKLOADS", "make_workload", "fixed_width_ranges", "half_bounded_ranges",
+           "sha256_of"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -157,6 +158,20 @@ def fixed_width_ranges(n: int, nq: int, frac: float, seed: int):
     l = (rng.random(nq) * (n - width + 1)).astype(np.int64)
     l = np.minimum(l, n - width)
     return l, l + width - 1
+
+
+def half_bounded_ranges(n: int, nq: int, lo: float, seed: int):
+    """nq half-bounded ranges: even queries are prefixes [0, w-1], odd ones
+    suffixes [n-w, n-1], widths log-uniform over [lo, n] points (the
+    half-bounded queries of the paper's Section 4.1 and Exp-1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo = min(float(n), float(lo))
+    width = np.clip(np.rint(np.exp(rng.uniform(math.log(lo), math.log(n), size=nq))), 1, n)
+    width = width.astype(np.int64)
+    pre = np.arange(nq) % 2 == 0
+    l = np.where(pre, 0, n - width).astype(np.int64)
+    r = np.where(pre, width - 1, n - 1).astype(np.int64)
+    return l, r
 
 
 def sha256_of(*arrays: np.ndarray) -> str:

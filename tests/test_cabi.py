@@ -116,6 +116,70 @@ def test_fanout_index_oracle_invariants(fanout_index):
     assert rec == 1.0
 
 
+@pytest.fixture(scope="module", params=[2, 3])
+def chain_index(request, tmp_path_factory):
+    B = request.param
+    w = synth.make_workload(0, n=3000, nq=0)
+    path = str(tmp_path_factory.mktemp(f"chain{B}") / "c.esgi")
+    esg.build_index(w["X"], w["attr"].astype(np.float64), path, degree=12, leaf=100,
+                    ef_construction=64, fanout=B, layout="chain")
+    return w, path, B
+
+
+def test_chain_builder_structure(chain_index, tmp_path):
+    """The half-bounded index (Section 4.1, Alg. 2): one graph per recorded
+    prefix [0, s_i - 1] and suffix [n - s_i, n - 1] (s_0 = n,
+    s_{i+1} = ceil(s_i / B), while s_i - 1 >= leaf); neighbours and entry
+    inside the recorded range, no self loops or repeats; O(N) rows in all
+    (2 sum s_i < 4N per chain pair); independent of the thread count."""
+    w, path, B = chain_index
+    ix = oracle.read_index(path)
+    assert ix.layout == 1 and ix.fanout == B and ix.c_den == B
+    sizes, starts = oracle.chain_levels(ix.n, ix.leaf, B)
+    assert ix.n_depth == len(sizes) and sizes[0] == ix.n
+    assert ix.adj.size == sum(sizes) * ix.degree and sum(sizes) < 2 * ix.n * B / (B - 1) + 4 * len(sizes)
+    for t, (sz, a) in enumerate(zip(sizes, starts)):
+        b = a + sz - 1
+        e = int(ix.ep[t + 1])
+        assert a <= e <= b
+        rows = ix.rows(t)[a:b + 1]
+        valid = rows != oracle.NO_NODE
+        assert np.all(np.diff(valid.astype(int), axis=1) <= 0)
+        vals = rows[valid].astype(np.int64)
+        assert np.all((vals >= a) & (vals <= b))
+        for i, row in enumerate(rows):
+            rv = row[row != oracle.NO_NODE].tolist()
+            assert len(set(rv)) == len(rv) and (a + i) not in rv
+    p1 = str(tmp_path / "c1.esgi")
+    esg.build_index(w["X"], w["attr"].astype(np.float64), p1, degree=12, leaf=100,
+                    ef_construction=64, fanout=B, layout="chain", threads=1)
+    assert open(p1, "rb").read() == open(path, "rb").read()
+    assert _load_status(path) in (esg.ESG_OK, esg.ESG_EHIP)
+
+
+def test_chain_index_exhaustive_equals_bruteforce(chain_index):
+    """Finding 1 on the half-bounded index: with a beam as large as the
+    recorded range, the search of the chosen prefix or suffix graph under
+    POST returns the exact filtered k-NN, for prefix, suffix and general
+    ranges; every query takes one part."""
+    w, path, B = chain_index
+    ix = oracle.read_index(path)
+    n = ix.n
+    Q = synth.make_workload(0, n=3000, nq=60)["Q"]
+    rng = np.random.default_rng(B)
+    r = rng.integers(0, n, 60)
+    l = np.where(np.arange(60) % 3 == 0, 0, np.where(np.arange(60) % 3 == 1, r, rng.integers(0, n, 60)))
+    l, r = np.minimum(l, r), np.where(np.arange(60) % 3 == 1, n - 1, np.maximum(l, r))
+    ids, dists, st, stats = oracle.query_batch(ix, Q, l, r, 10, 4096, 4096, with_stats=True)
+    assert np.all(st == 0) and np.all(stats[:, 0] == 1)
+    pos_of = np.empty(n, np.int64)
+    pos_of[ix.ext_id] = np.arange(n)
+    pos = np.where(ids >= 0, pos_of[np.maximum(ids, 0)], -1)
+    gt_pos, gt_d = oracle.bruteforce(ix.vec, Q, l, r, 10)
+    rec, _, _ = oracle.recall(ix.vec, Q, l, r, pos, gt_pos, gt_d, 10)
+    assert rec == 1.0
+
+
 def test_builder_fanout_errors(tmp_path):
     X = np.zeros((10, 4), np.float32)
     with pytest.raises(esg.EsgError) as e:

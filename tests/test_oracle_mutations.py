@@ -42,6 +42,11 @@ MUTATIONS = {
     "child_start_floor": ("return a + (j * L + f - 1) / f;", "return a + (j * L) / f;"),
     # child numbering off by one
     "child_heap": ("(int64_t)s->fanout * (heap - 1) + 2 + j,", "(int64_t)s->fanout * (heap - 1) + 1 + j,"),
+    # half-bounded index: prefix sizes halved with the division rounded down
+    "chain_floor": ("    int64_t nx = (sp + base - 1) / base;\n    if (nx == sp || nx < rq + 1) break;",
+                    "    int64_t nx = sp / base;\n    if (nx == sp || nx < rq + 1) break;"),
+    # half-bounded index: the tie between the two sides goes to the suffix
+    "chain_tie": ("else use_prefix = ss >= sp;", "else use_prefix = ss > sp;"),
     # strict elastic comparison
     "elastic_strict": ("return (int64_t)c_den * (y - x + 1) >= (b - a + 1);",
                        "return (int64_t)c_den * (y - x + 1) > (b - a + 1);"),

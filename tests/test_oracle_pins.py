@@ -110,6 +110,71 @@ def test_fanout_lemma_needs_c_at_most_one_over_f():
     assert worst > 2
 
 
+def test_selector_1d_golden_cases():
+    """The half-bounded index's query rule (Section 4.1, Lemma 4.1) worked by
+    hand (tests/golden/selector_cases_1d.txt)."""
+    n_cases = 0
+    for line in open(os.path.join(GOLD, "selector_cases_1d.txt")):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        lhs, rhs = line.split("|")
+        n, leaf, B, l, r = map(int, lhs.split())
+        parts, cnt = oracle.select_1d(n, leaf, l, r, base=B)
+        assert cnt == 1 and parts == _parse_parts(rhs), (n, leaf, B, l, r, parts)
+        n_cases += 1
+    assert n_cases >= 17
+
+
+def _recorded_sizes(n, B):
+    s, out = n, [n]
+    while s > 1:
+        s = -(-s // B)
+        out.append(s)
+    return out
+
+
+@pytest.mark.parametrize("n,leaf,B", [(1, 1, 2), (2, 1, 2), (37, 1, 2), (100, 4, 2), (257, 8, 2),
+                                      (90, 2, 3), (200, 5, 4), (500, 16, 8)])
+def test_selector_1d_half_bounded(n, leaf, B):
+    """Lemma 4.1 by enumeration: every prefix [0, r] and suffix [l, n-1] gets
+    one recorded range holding it -- the smallest recorded one (no smaller
+    recorded size holds it) -- whose ratio is >= 1/B when it owns a graph;
+    a range whose tightest recorded size has no graph is scanned."""
+    sizes = _recorded_sizes(n, B)
+    K = sum(1 for s in sizes if s - 1 >= leaf)
+    for r in range(n):
+        for (l, rr, pre) in ((0, r, True), (r, n - 1, False)):
+            if not pre and l == 0:
+                continue
+            (p,), cnt = oracle.select_1d(n, leaf, l, rr, base=B)
+            w = rr - l + 1
+            tight = min(s for s in sizes if s >= w)
+            assert (p["x"], p["y"]) == (l, rr)
+            assert (p["a"], p["b"]) == ((0, tight - 1) if pre else (n - tight, n - 1))
+            if tight - 1 >= leaf:
+                i = sizes.index(tight)
+                assert p["kind"] == oracle.KIND_GRAPH and B * w >= tight
+                assert p["depth"] == (i if pre else K + i) and p["heap"] == p["depth"] + 1
+            else:
+                assert p["kind"] == oracle.KIND_SCAN
+
+
+def test_selector_1d_general_ranges_take_the_better_side():
+    """A range with both ends inside (outside the half-bounded index's own
+    scope) takes the tighter cover of the two sides (larger ratio; the
+    prefix on a tie), still one part holding it."""
+    n, leaf, B = 300, 4, 2
+    sizes = _recorded_sizes(n, B)
+    for l in range(1, n - 1, 7):
+        for r in range(l, n - 1, 5):
+            (p,), _ = oracle.select_1d(n, leaf, l, r, base=B)
+            sp = min(s for s in sizes if s >= r + 1)
+            ss = min(s for s in sizes if s >= n - l)
+            want = (0, sp - 1) if ss >= sp else (n - ss, n - 1)
+            assert (p["a"], p["b"]) == want and p["a"] <= l and r <= p["b"]
+
+
 @pytest.mark.parametrize("n,leaf,f", [(50, 1, 2), (100, 3, 2), (1000, 16, 2), (4096, 64, 2),
                                       (100, 1, 4), (1000, 16, 8), (4096, 64, 16)])
 def test_selector_half_bounded_one_part(n, leaf, f):
