@@ -56,14 +56,15 @@ extern "C" {
 #define ESG_FANOUT_MAX 64    /* largest segment-tree fanout accepted        */
 #define ESG_NO_NODE 0xFFFFFFFFu /* padding value of an adjacency row        */
 
-/* ---- index file (version 1), little-endian ------------------------------
+/* ---- index file (version 2), little-endian ------------------------------
  * bytes [0,512): header
  *   char     magic[8]  = "ESGIDX01"
- *   uint32   version   = 1, header_bytes = 512
+ *   uint32   version   = 2, header_bytes = 512
  *   int64    n;  int32 d, degree, leaf, fanout, n_depth, c_den, ef_construction, layout
  *   uint64   off_ids, off_attr, off_vec, off_adj, off_ep, file_bytes
  *   uint32   crc32c of the sections ids, attr, vec, adj, ep (in that order)
- *   uint32   crc32c of header bytes [0,124)
+ *   int32    metric, dq;  float64 max_norm2   (see ESG_METRIC_*)
+ *   uint32   crc32c of header bytes [0,140)
  * sections (each 4096-aligned):
  *   ids  int64  [n]                external id of the point at position p
  *   attr float64[n]                sorted attribute values (rank -> value)
@@ -91,6 +92,26 @@ extern "C" {
  *   graph is scanned.
  * ----------------------------------------------------------------------- */
 
+/* Metrics.  Every index searches by squared Euclidean distance over its
+ * stored vectors; the other metrics are reduced to it when the index is
+ * built (the paper states its method for Euclidean space and leaves other
+ * metrics open, Section 7):
+ *   ESG_METRIC_L2       stored = input; dq = d.
+ *   ESG_METRIC_ANGULAR  stored = input / |input| (float64 norm, rounded to
+ *       float32); dq = d.  For a query q the distance is 1 + |q|^2 - 2 cos
+ *       (x, q) |q|, so the order is that of decreasing cosine similarity.
+ *   ESG_METRIC_IP       maximum inner product by the one-coordinate
+ *       Euclidean transform of Bachrach et al. (RecSys 2014): with
+ *       M^2 = max |x|^2, stored x' = [x, sqrt(M^2 - |x|^2)] (d = input d + 1)
+ *       and a query of dq = d - 1 values is read as [q, 0], so
+ *       |x' - q'|^2 = M^2 + |q|^2 - 2 <x, q>: increasing distance is
+ *       decreasing inner product, and <x, q> = (M^2 + |q|^2 - dist) / 2.
+ * Search calls take queries of dq float32 values per row and return the
+ * stored-space squared distance. */
+#define ESG_METRIC_L2 0
+#define ESG_METRIC_ANGULAR 1
+#define ESG_METRIC_IP 2
+
 typedef struct {
   int32_t degree;          /* max out-degree R of every graph (<= 32), 16   */
   int32_t leaf;            /* leaf bound: node [a,b] has a graph iff b-a >= leaf (>= 1) */
@@ -103,10 +124,12 @@ typedef struct {
   int32_t layout;          /* 0: segment tree (HBI-2D, Section 4.2); 1: the
                               half-bounded index (HBI-1D, Section 4.1):
                               prefix and suffix chains with base = fanout */
+  int32_t metric;          /* ESG_METRIC_L2 (0), _ANGULAR or _IP            */
 } esg_build_params;
 
 /* Builds the HBI-2D index of Alg. 3 on the host and writes it to out_path.
- * vecs: host float32 [n][d] row-major, point i = external id i.
+ * vecs: host float32 [n][d] row-major, point i = external id i; d is the
+ *       input length (the stored length is d + 1 for ESG_METRIC_IP).
  * attr: host float64 [n] attribute values (any order; equal values are
  *       ranked by external id).  The library ranks them itself, so
  *       positions are attribute ranks (ties by external id).
@@ -117,8 +140,10 @@ typedef struct {
  * width ef_construction followed by occlusion pruning (Section 2.1) to at
  * most `degree` neighbours and reverse edges.  Points are inserted in
  * deterministic batches, so the file does not depend on `threads`.
- * Errors: EINVAL (null/size), EUNSUPPORTED (fanout > ESG_FANOUT_MAX),
- * ERANGE (tree too deep), ENOMEM, EIO. */
+ * Errors: EINVAL (null/size, unknown metric, a zero or non-finite vector
+ * under ESG_METRIC_ANGULAR, a non-finite norm under ESG_METRIC_IP),
+ * EUNSUPPORTED (fanout > ESG_FANOUT_MAX), ERANGE (tree too deep), ENOMEM,
+ * EIO. */
 int32_t esg_build_index(const float* vecs, const double* attr, int64_t n, int32_t d,
                         const esg_build_params* params, const char* out_path);
 
@@ -130,12 +155,17 @@ typedef struct {
   int32_t d, degree, leaf, fanout, n_depth, c_den;
   int32_t has_bf16, has_fp8;  /* device copies made by esg_index_add_storage */
   int64_t device_bytes;       /* device memory owned by the index           */
+  int32_t metric, dq;         /* ESG_METRIC_*; values per query row         */
+  double max_norm2;           /* ESG_METRIC_IP: M^2; else 0                 */
 } esg_index_info_t;
 
 /* Reads the index file, checks magic, sizes and checksums, and copies it to
  * HIP device `hip_device` (plus the fixed search workspace).  On success
- * *out owns all of it until esg_free_index.  Errors: EINVAL, EIO, EFORMAT,
- * ENOMEM, EHIP. */
+ * *out owns all of it until esg_free_index.  Kernels are compiled for the
+ * stored lengths 32, 64, 96, 128, 256, 512, 768, 1024 and 2048; each serves
+ * every length with the same number of lanes per vector and chunks per
+ * lane, which covers d = 17 .. 1024 and 1793 .. 2048.  Errors: EINVAL,
+ * EIO, EFORMAT, ENOMEM, EHIP, EUNSUPPORTED (a length no kernel serves). */
 int32_t esg_load_index(const char* path, int32_t hip_device, esg_index** out);
 
 /* Adds a reduced-precision traversal copy of the vectors on the device:
@@ -271,8 +301,8 @@ typedef struct {
  * certified are rescanned exactly.  The result equals a float32 scan of
  * [l,r].  Same buffers as esg_search_batch; k <= 128.  Copies l and r to
  * the host to plan the windows and synchronizes `stream` before returning.
- * Needs bfloat16 storage and a reservation.  Errors: EINVAL, EUNSUPPORTED,
- * ERANGE, EHIP. */
+ * Needs bfloat16 storage and a reservation, and stored rows of at most
+ * 1,024 values.  Errors: EINVAL, EUNSUPPORTED, ERANGE, EHIP. */
 int32_t esg_scan_batch(esg_index* idx, const esg_scan_opts* opts, const float* queries,
                        const int64_t* l, const int64_t* r, int64_t nq, int32_t k,
                        int64_t* ids, float* dists, void* stream);

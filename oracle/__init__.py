@@ -27,6 +27,11 @@ Contents and the passage each follows:
                              12-64-64-1 ReLU network that predicts ef.
 * ``adam_step64``         -- one Adam step (Kingma and Ba, Algorithm 1) in
                              float64.
+* ``metric_store64``      -- the vectors an angular or inner-product index
+                             stores (unit rows; the Euclidean transform of
+                             Bachrach et al. 2014), in float64.
+* ``exact_metric``        -- exact filtered top-k by Euclidean distance,
+                             cosine similarity or inner product, in float64.
 """
 from __future__ import annotations
 
@@ -43,6 +48,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 KIND_GRAPH, KIND_SCAN = 1, 2
 DIST_F32, DIST_BF16, DIST_FP8 = 0, 1, 2
+METRIC_L2, METRIC_ANGULAR, METRIC_IP = 0, 1, 2   # the index file's metric field
 NO_NODE = 0xFFFFFFFF
 
 
@@ -134,8 +140,11 @@ class OracleIndex:
     """Arrays of one index in host memory plus the C view the oracle uses."""
 
     def __init__(self, n, d, degree, leaf, n_depth, c_den, ext_id, attr, vec, adj, ep, fanout=2,
-                 layout=0, row_base=None):
+                 layout=0, row_base=None, metric=METRIC_L2, dq=None, max_norm2=0.0):
         self.n, self.d, self.degree, self.leaf = int(n), int(d), int(degree), int(leaf)
+        # metric the stored vectors were made from; a query row holds dq values
+        self.metric, self.max_norm2 = int(metric), float(max_norm2)
+        self.dq = self.d if dq is None else int(dq)
         self.n_depth, self.c_den, self.fanout = int(n_depth), int(c_den), int(fanout)
         self.layout = int(layout)
         # row of position p at depth t: adj_flat[(row_base[t] + p) * degree]
@@ -157,6 +166,19 @@ class OracleIndex:
         if self.layout == 1:
             return select_1d(self.n, self.leaf, int(lq), int(rq), base=self.fanout)
         return select(self.n, self.leaf, int(lq), int(rq), c_den=self.c_den, fanout=self.fanout)
+
+    def stored_query(self, q) -> np.ndarray:
+        """A query as the search reads it: its dq values, then zeros up to
+        the stored length d (the inner-product transform's last coordinate
+        of a query is 0)."""
+        q = np.asarray(q, np.float32)
+        if q.shape[-1] == self.d:
+            return np.ascontiguousarray(q)
+        if q.shape[-1] != self.dq:
+            raise ValueError("query length")
+        out = np.zeros(q.shape[:-1] + (self.d,), np.float32)
+        out[..., :self.dq] = q
+        return out
 
     def rows(self, depth: int):
         """Adjacency rows of a depth, indexed by position (a view)."""
@@ -187,15 +209,18 @@ class OracleIndex:
 
 def read_index(path: str) -> OracleIndex:
     with open(path, "rb") as f:
-        head = f.read(128)
-    if len(head) < 128 or head[:8] != b"ESGIDX01":
+        head = f.read(144)
+    if len(head) < 144 or head[:8] != b"ESGIDX01":
         raise ValueError("not an index file")
     version, header_bytes = struct.unpack_from("<II", head, 8)
     n, = struct.unpack_from("<q", head, 16)
     d, degree, leaf, fanout, n_depth, c_den, efc, layout = struct.unpack_from("<8i", head, 24)
     off_ids, off_attr, off_vec, off_adj, off_ep, file_bytes = struct.unpack_from("<6Q", head, 56)
-    if version != 1 or fanout < 2:
+    metric, dq = struct.unpack_from("<2i", head, 124)
+    max_norm2, = struct.unpack_from("<d", head, 132)
+    if version != 2 or fanout < 2:
         raise ValueError("unsupported index version/fanout")
+    mkw = dict(metric=metric, dq=dq, max_norm2=max_norm2)
     mm = np.memmap(path, dtype=np.uint8, mode="r")
     if mm.size != file_bytes:
         raise ValueError("truncated index file")
@@ -213,10 +238,11 @@ def read_index(path: str) -> OracleIndex:
         adj = sect(off_adj, np.uint32, int(sum(sizes)) * degree)
         ep = sect(off_ep, np.uint32, n_depth + 1)
         return OracleIndex(n, d, degree, leaf, n_depth, c_den, ext_id, attr, vec, adj, ep, fanout,
-                           layout=1, row_base=row_base)
+                           layout=1, row_base=row_base, **mkw)
     adj = sect(off_adj, np.uint32, n_depth * n * degree).reshape(n_depth, n, degree)
     ep = sect(off_ep, np.uint32, node_numbers(fanout, n_depth))
-    return OracleIndex(n, d, degree, leaf, n_depth, c_den, ext_id, attr, vec, adj, ep, fanout)
+    return OracleIndex(n, d, degree, leaf, n_depth, c_den, ext_id, attr, vec, adj, ep, fanout,
+                       **mkw)
 
 
 def chain_levels(n: int, leaf: int, base: int):
@@ -372,7 +398,7 @@ def search_part(ix: OracleIndex, part: dict, q: np.ndarray, m: int, cap_p: int |
                 hop_budget: int = -1, kind: int = DIST_F32, visited_cap: int = 1 << 22):
     """Alg. 1 + POST on the node of ``part``.  Returns (dists, positions,
     visited (discovery order), hops, status)."""
-    q = np.ascontiguousarray(q, np.float32)
+    q = ix.stored_query(q)
     cap_p = m if cap_p is None else cap_p
     qd = np.zeros(m, np.float32)
     qp = np.zeros(m, np.int64)
@@ -400,7 +426,7 @@ def search_part_learned(ix: OracleIndex, part: dict, q, ef_max: int, switch_hop:
     at m = cap = ef_max, keep the ef2 best of P and Q and continue with
     m = cap = ef2 (ef2 <= 0: features only).  Returns (dists, positions,
     visited, hops, status, float64 features (12) or None)."""
-    q = np.ascontiguousarray(q, np.float32)
+    q = ix.stored_query(q)
     qd = np.zeros(ef_max, np.float32)
     qp = np.zeros(ef_max, np.int64)
     ql = np.zeros(1, np.int32)
@@ -423,7 +449,7 @@ def query_learned(ix: OracleIndex, q, lq, rq, k, ef_max, switch_hop, ef2_parts, 
     """Alg. 4 where graph part i switches to ef2_parts[i] after switch_hop
     expansions (the beam widths a predictor chose), or, with hop2_parts,
     stops after hop2_parts[i] further expansions (the stopping steps)."""
-    q = np.ascontiguousarray(q, np.float32)
+    q = ix.stored_query(q)
     ids = np.zeros(k, np.int64)
     dists = np.zeros(k, np.float32)
     stats = np.zeros(8, np.int64)
@@ -435,7 +461,7 @@ def query_learned(ix: OracleIndex, q, lq, rq, k, ef_max, switch_hop, ef2_parts, 
 
 
 def query(ix: OracleIndex, q, lq, rq, k, ef, cap_p=None, hop_budget=-1, kind=DIST_F32, rerank=0):
-    q = np.ascontiguousarray(q, np.float32)
+    q = ix.stored_query(q)
     ids = np.zeros(k, np.int64)
     dists = np.zeros(k, np.float32)
     stats = np.zeros(8, np.int64)
@@ -446,7 +472,7 @@ def query(ix: OracleIndex, q, lq, rq, k, ef, cap_p=None, hop_budget=-1, kind=DIS
 
 def query_batch(ix: OracleIndex, Q, l, r, k, ef, cap_p=None, hop_budget=-1, kind=DIST_F32,
                 rerank=0, with_stats=False):
-    Q = np.ascontiguousarray(Q, np.float32)
+    Q = ix.stored_query(Q)
     l = np.ascontiguousarray(l, np.int64)
     r = np.ascontiguousarray(r, np.int64)
     nq = Q.shape[0]
@@ -509,6 +535,64 @@ def recall(vec_pos, Q, l, r, pos_found, gt_pos, gt_dist, k):
         rec[i] = min(kk, int(np.sum(df <= dk))) / kk
         strict[i] = len(np.intersect1d(found, gt_pos[i][:kk])) / kk
     return float(rec.mean()), float(strict.mean()), rec
+
+
+# --------------------------------------------------------------------------
+# Other metrics.  The paper states the method for Euclidean distance and
+# names inner product and angular distance as open (Section 7); the index
+# reduces them to Euclidean distance over transformed vectors.
+# --------------------------------------------------------------------------
+
+def metric_store64(X, metric: int):
+    """The vectors an index of the given metric stores, in float64, and M^2.
+
+    Angular: every row scaled to unit norm; then |x - q|^2 = 1 + |q|^2 -
+    2 |q| cos(x, q), so increasing distance is decreasing cosine.  Inner
+    product: the one-coordinate transform of Bachrach et al. (RecSys 2014),
+    x' = [x, sqrt(M^2 - |x|^2)] with M^2 the largest squared norm, and a
+    query q' = [q, 0]; then |x' - q'|^2 = M^2 + |q|^2 - 2 <x, q>."""
+    X = np.asarray(X, np.float64)
+    n2 = np.sum(X * X, axis=1)
+    if metric == METRIC_L2:
+        return X.copy(), 0.0
+    if metric == METRIC_ANGULAR:
+        return X / np.sqrt(n2)[:, None], 0.0
+    if metric == METRIC_IP:
+        m2 = float(n2.max())
+        return np.hstack([X, np.sqrt(np.maximum(m2 - n2, 0.0))[:, None]]), m2
+    raise ValueError("metric")
+
+
+def exact_metric(X_pos, Q, l, r, k: int, metric: int):
+    """Exact range-filtered top-k under a metric, from its definition, in
+    float64 over the original vectors in position order: squared Euclidean
+    distance increasing, cosine similarity decreasing, or inner product
+    decreasing; ties by position.  Returns (positions [nq,k], -1 pad;
+    scores [nq,k] float64: the distance, cosine or inner product; nan pad)."""
+    X = np.asarray(X_pos, np.float64)
+    Q = np.atleast_2d(np.asarray(Q, np.float64))
+    l, r = np.atleast_1d(l), np.atleast_1d(r)
+    nq = Q.shape[0]
+    pos = np.full((nq, k), -1, np.int64)
+    score = np.full((nq, k), np.nan)
+    for i in range(nq):
+        a, b = int(l[i]), int(r[i])
+        seg, q = X[a:b + 1], Q[i]
+        if metric == METRIC_L2:
+            s = np.sum((seg - q) ** 2, axis=1)
+            key = s
+        elif metric == METRIC_ANGULAR:
+            s = (seg @ q) / (np.sqrt(np.sum(seg * seg, axis=1)) * np.sqrt(q @ q))
+            key = -s
+        elif metric == METRIC_IP:
+            s = seg @ q
+            key = -s
+        else:
+            raise ValueError("metric")
+        order = np.lexsort((np.arange(len(seg)), key))[:k]
+        pos[i, :len(order)] = a + order
+        score[i, :len(order)] = s[order]
+    return pos, score
 
 
 # --------------------------------------------------------------------------

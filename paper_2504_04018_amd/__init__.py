@@ -36,11 +36,15 @@ class EsgError(RuntimeError):
         self.status = status
 
 
+METRICS = {"l2": 0, "angular": 1, "ip": 2}   # ESG_METRIC_*
+
+
 class BuildParams(ctypes.Structure):
     _fields_ = [("degree", ctypes.c_int32), ("leaf", ctypes.c_int32),
                 ("ef_construction", ctypes.c_int32), ("fanout", ctypes.c_int32),
                 ("threads", ctypes.c_int32), ("batch_max", ctypes.c_int32),
-                ("verbose", ctypes.c_int32), ("layout", ctypes.c_int32)]
+                ("verbose", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("metric", ctypes.c_int32)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -48,7 +52,8 @@ class IndexInfo(ctypes.Structure):
                 ("leaf", ctypes.c_int32), ("fanout", ctypes.c_int32),
                 ("n_depth", ctypes.c_int32), ("c_den", ctypes.c_int32),
                 ("has_bf16", ctypes.c_int32), ("has_fp8", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("metric", ctypes.c_int32),
+                ("dq", ctypes.c_int32), ("max_norm2", ctypes.c_double)]
 
 
 class PartTrace(ctypes.Structure):
@@ -132,17 +137,20 @@ def _check(status: int, what: str):
 
 def build_index(X: np.ndarray, attr: np.ndarray, path: str, degree: int = 16, leaf: int = 1024,
                 ef_construction: int = 200, threads: int = 0, batch_max: int = 0,
-                verbose: bool = False, fanout: int = 2, layout: str = "tree") -> None:
+                verbose: bool = False, fanout: int = 2, layout: str = "tree",
+                metric: str = "l2") -> None:
     """esg_build_index: host build of the index file -- layout "tree": the
     HBI-2D segment tree (Alg. 3) of the given fanout (elastic constant
     1/fanout); layout "chain": the half-bounded HBI-1D index (Alg. 2),
-    prefix and suffix graphs of sizes N, ceil(N/B), ... with B = fanout."""
+    prefix and suffix graphs of sizes N, ceil(N/B), ... with B = fanout.
+    metric "l2", "angular" (rows stored at unit norm) or "ip" (maximum inner
+    product: rows stored as [x, sqrt(M^2 - |x|^2)], queries stay [n, d])."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     attr = np.ascontiguousarray(attr, dtype=np.float64)
     if X.ndim != 2 or attr.shape != (X.shape[0],):
         raise ValueError("X must be [n,d] and attr [n]")
     p = BuildParams(degree, leaf, ef_construction, fanout, threads, batch_max, int(verbose),
-                    {"tree": 0, "chain": 1}[layout])
+                    {"tree": 0, "chain": 1}[layout], METRICS[metric])
     st = lib().esg_build_index(X.ctypes.data, attr.ctypes.data, X.shape[0], X.shape[1],
                                ctypes.byref(p), path.encode())
     _check(st, "esg_build_index")
@@ -175,6 +183,9 @@ class Index:
         self.path = path
         inf = self.info()
         self.n, self.d = inf["n"], inf["d"]
+        self.dq = inf["dq"]             # values per query row
+        self.metric = {v: k for k, v in METRICS.items()}[inf["metric"]]
+        self.max_norm2 = inf["max_norm2"]
 
     def info(self) -> dict:
         out = IndexInfo()
@@ -211,7 +222,7 @@ class Index:
         import torch
         nq = queries.shape[0]
         dev = queries.device
-        qp = _dev(queries, torch.float32, (nq, self.d), "queries")
+        qp = _dev(queries, torch.float32, (nq, self.dq), "queries")
         lp = _dev(l, torch.int64, (nq,), "l")
         rp = _dev(r, torch.int64, (nq,), "r")
         if ids is None:
@@ -242,7 +253,7 @@ class Index:
         import torch
         nq = queries.shape[0]
         dev = queries.device
-        qp = _dev(queries, torch.float32, (nq, self.d), "queries")
+        qp = _dev(queries, torch.float32, (nq, self.dq), "queries")
         lp = _dev(l, torch.int64, (nq,), "l")
         rp = _dev(r, torch.int64, (nq,), "r")
         if ids is None:

@@ -361,10 +361,16 @@ bool pad_to(FILE* f, uint64_t off) {
   return true;
 }
 
+// What the stored vectors were made from (esg.h, ESG_METRIC_*).
+struct MetricInfo {
+  int32_t metric = ESG_METRIC_L2, dq = 0;
+  double max_norm2 = 0.0;
+};
+
 // Writes the index file (layout documented in esg.h).
 int32_t write_index(const char* out_path, int64_t n, int32_t d, const esg_build_params& P,
-                    int fanout, int n_depth, int layout, const int64_t* ids, const double* attr,
-                    const float* X, const std::vector<uint32_t>& adj,
+                    int fanout, int n_depth, int layout, const MetricInfo& mi, const int64_t* ids,
+                    const double* attr, const float* X, const std::vector<uint32_t>& adj,
                     const std::vector<uint32_t>& ep) {
   const uint64_t adj_bytes = (uint64_t)adj.size() * 4, ep_bytes = (uint64_t)ep.size() * 4;
   esg::FileHeader h;
@@ -381,6 +387,9 @@ int32_t write_index(const char* out_path, int64_t n, int32_t d, const esg_build_
   h.c_den = fanout;   // elastic constant c = 1/fanout (Lemma 4.3; Lemma 4.1 with base B)
   h.layout = layout;
   h.ef_construction = P.ef_construction;
+  h.metric = mi.metric;
+  h.dq = mi.dq;
+  h.max_norm2 = mi.max_norm2;
   h.off_ids = esg::align_up(esg::kHeaderBytes);
   h.off_attr = esg::align_up(h.off_ids + esg::bytes_ids(n));
   h.off_vec = esg::align_up(h.off_attr + esg::bytes_attr(n));
@@ -442,7 +451,8 @@ void build_chain(Builder& B, const std::vector<int64_t>& sizes, std::vector<uint
 
 int32_t build_chains(const float* X, const std::vector<int64_t>& order,
                      const std::vector<double>& sorted_attr, int64_t n, int32_t d,
-                     const esg_build_params& P, int fanout, const char* out_path) {
+                     const esg_build_params& P, int fanout, const MetricInfo& mi,
+                     const char* out_path) {
   const std::vector<int64_t> sizes = esg::chain_sizes(n, P.leaf, fanout);
   const size_t k = sizes.size();
   if (k == 0 || 2 * k > 40) return ESG_ERANGE;
@@ -484,8 +494,8 @@ int32_t build_chains(const float* X, const std::vector<int64_t>& order,
     ep[1 + i] = eps_p[i];
     ep[1 + k + i] = (uint32_t)(n - 1 - (int64_t)eps_s[i]);
   }
-  return write_index(out_path, n, d, P, fanout, (int)(2 * k), 1, order.data(), sorted_attr.data(), X,
-                     adj, ep);
+  return write_index(out_path, n, d, P, fanout, (int)(2 * k), 1, mi, order.data(),
+                     sorted_attr.data(), X, adj, ep);
 }
 
 }  // namespace
@@ -496,7 +506,8 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
     return ESG_EINVAL;
   const esg_build_params& P = *params;
   if (P.degree < 1 || P.degree > ESG_DEGREE_MAX || P.leaf < 1 || P.ef_construction < 1 ||
-      P.fanout < 0 || P.fanout == 1 || P.layout < 0 || P.layout > 1)
+      P.fanout < 0 || P.fanout == 1 || P.layout < 0 || P.layout > 1 ||
+      P.metric < ESG_METRIC_L2 || P.metric > ESG_METRIC_IP || d >= 65536)
     return ESG_EINVAL;
   const int fanout = P.fanout == 0 ? 2 : P.fanout;
   if (fanout > ESG_FANOUT_MAX) return ESG_EUNSUPPORTED;
@@ -512,15 +523,46 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
     std::stable_sort(order.begin(), order.end(),
                      [&](int64_t u, int64_t v) { return attr[u] < attr[v]; });
     std::vector<double> sorted_attr((size_t)n);
-    std::vector<float> X((size_t)n * (size_t)d);
+    MetricInfo mi;
+    mi.metric = P.metric;
+    mi.dq = d;
+    // Other metrics become squared Euclidean distance over transformed
+    // vectors: unit rows (angular), or one extra coordinate that brings
+    // every row to norm M (inner product, the Euclidean transform of
+    // Bachrach et al. 2014).  Norms are summed in float64.
+    std::vector<double> norm2((size_t)n);
+    bool bad = false;
+#pragma omp parallel for schedule(static) reduction(|| : bad)
+    for (int64_t i = 0; i < n; i++) {
+      const float* v = vecs + (size_t)i * d;
+      double s2 = 0.0;
+      for (int32_t j = 0; j < d; j++) s2 += (double)v[j] * (double)v[j];
+      norm2[(size_t)i] = s2;
+      bad = bad || !std::isfinite(s2) || (P.metric == ESG_METRIC_ANGULAR && s2 == 0.0);
+    }
+    if (bad && P.metric != ESG_METRIC_L2) return ESG_EINVAL;
+    if (P.metric == ESG_METRIC_IP)
+      for (int64_t i = 0; i < n; i++) mi.max_norm2 = std::max(mi.max_norm2, norm2[(size_t)i]);
+    const int32_t ds = P.metric == ESG_METRIC_IP ? d + 1 : d;   // stored length
+    std::vector<float> X((size_t)n * (size_t)ds);
 #pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < n; p++) {
-      sorted_attr[(size_t)p] = attr[order[(size_t)p]];
-      std::memcpy(&X[(size_t)p * d], vecs + (size_t)order[(size_t)p] * d, sizeof(float) * d);
+      const int64_t i = order[(size_t)p];
+      sorted_attr[(size_t)p] = attr[i];
+      const float* src = vecs + (size_t)i * d;
+      float* dst = &X[(size_t)p * ds];
+      if (P.metric == ESG_METRIC_ANGULAR) {
+        const double inv = 1.0 / std::sqrt(norm2[(size_t)i]);
+        for (int32_t j = 0; j < d; j++) dst[j] = (float)((double)src[j] * inv);
+      } else {
+        std::memcpy(dst, src, sizeof(float) * d);
+      }
+      if (P.metric == ESG_METRIC_IP)
+        dst[d] = (float)std::sqrt(std::max(mi.max_norm2 - norm2[(size_t)i], 0.0));
     }
 
     if (P.layout == 1)
-      return build_chains(X.data(), order, sorted_attr, n, d, P, fanout, out_path);
+      return build_chains(X.data(), order, sorted_attr, n, ds, P, fanout, mi, out_path);
     std::vector<NodeRef> nodes;
     collect(0, n - 1, 0, 1, P.leaf, fanout, nodes);
     int n_depth = 0;
@@ -529,7 +571,7 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
 
     Builder B;
     B.n = n;
-    B.d = d;
+    B.d = ds;
     B.R = P.degree;
     B.leaf = P.leaf;
     B.efc = P.ef_construction;
@@ -567,7 +609,7 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
                 t, level.size(), (long long)repaired);
     }
 
-    return write_index(out_path, n, d, P, fanout, n_depth, 0, order.data(), sorted_attr.data(),
+    return write_index(out_path, n, ds, P, fanout, n_depth, 0, mi, order.data(), sorted_attr.data(),
                        X.data(), adj, ep);
   } catch (const std::bad_alloc&) {
     return ESG_ENOMEM;

@@ -10,7 +10,7 @@
 namespace esg {
 
 constexpr char kMagic[8] = {'E', 'S', 'G', 'I', 'D', 'X', '0', '1'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 constexpr uint32_t kHeaderBytes = 512;
 constexpr uint64_t kAlign = 4096;
 
@@ -23,11 +23,14 @@ struct FileHeader {
   int32_t d, degree, leaf, fanout, n_depth, c_den, ef_construction, layout;
   uint64_t off_ids, off_attr, off_vec, off_adj, off_ep, file_bytes;
   uint32_t crc_sections[5];
-  uint32_t crc_header;  // crc32c of bytes [0, offsetof(crc_header))
+  int32_t metric;      // ESG_METRIC_*: what the stored vectors were made from
+  int32_t dq;          // query length: d, or d - 1 for the inner-product transform
+  double max_norm2;    // inner product: M^2, the largest squared norm; else 0
+  uint32_t crc_header; // crc32c of bytes [0, offsetof(crc_header))
 };
 #pragma pack(pop)
-static_assert(sizeof(FileHeader) == 128, "header layout");
-static_assert(offsetof(FileHeader, crc_header) == 124, "header layout");
+static_assert(sizeof(FileHeader) == 144, "header layout");
+static_assert(offsetof(FileHeader, crc_header) == 140, "header layout");
 
 inline uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 

@@ -41,11 +41,12 @@ struct SearchArgs {
   const int64_t* ext_id;  // [n]
   int64_t n;
   int32_t d, dp, R, leaf, n_depth, c_den;
+  int32_t dq;             // values per query row (<= d; the rest of a query reads as 0)
   int32_t fanout;         // children per tree node (the chains' base in layout 1)
   int32_t layout;         // 0: segment tree; 1: prefix and suffix chains (half-bounded index)
   const int64_t* row_base;// [n_depth]: row of position p at depth t is adj + (row_base[t] + p) R
   // batch
-  const float* queries;   // [nq][d]
+  const float* queries;   // [nq][dq]
   const int64_t* l;
   const int64_t* r;
   int64_t nq;

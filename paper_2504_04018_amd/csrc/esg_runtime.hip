@@ -60,6 +60,8 @@ struct esg_index {
   int device = 0;
   int64_t n = 0;
   int32_t d = 0, dp = 0, R = 0, leaf = 0, n_depth = 0, c_den = 2, fanout = 2, layout = 0;
+  int32_t metric = 0, dq = 0;   // ESG_METRIC_*; values per query row
+  double max_norm2 = 0.0;
   int64_t* row_base = nullptr;  // [n_depth] device: row of position p at depth t = row_base[t] + p
   float* vec = nullptr;
   uint16_t* vec16 = nullptr;
@@ -340,6 +342,25 @@ bool tree_is_consistent(int64_t n, int32_t leaf, int32_t fanout, int32_t n_depth
   return true;
 }
 
+// Lanes per vector for C chunks: the next power of two, at most a wave.
+int lanes_for_chunks(int64_t c) {
+  int g = 1;
+  while (g < c) g *= 2;
+  return g > 64 ? 64 : g;
+}
+
+// A kernel table compiled for dimension cls serves dimension d when every
+// storage type (4, 8, 16 values per 16-byte chunk) has the same lanes per
+// vector and chunks per lane, and d's padded row fits cls's.
+bool same_shape(int64_t d, int64_t cls) {
+  for (int w : {4, 8, 16}) {
+    const int64_t c = (d + w - 1) / w, cc = (cls + w - 1) / w;
+    const int g = lanes_for_chunks(c), gc = lanes_for_chunks(cc);
+    if (g != gc || (c + g - 1) / g != (cc + gc - 1) / gc) return false;
+  }
+  return (d + 15) / 16 <= (cls + 15) / 16;
+}
+
 int width_index(int cap) {
   if (cap <= 64) return 0;
   if (cap <= 128) return 1;
@@ -368,6 +389,11 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
       h.n_depth < 0 || h.n_depth > 40 || h.c_den < h.fanout || h.layout < 0 || h.layout > 1 ||
       (h.layout == 0 && esg::ep_count(h.n_depth, h.fanout) == 0))
     return ESG_EFORMAT;   // c = 1/c_den <= 1/fanout keeps Alg. 4 at two parts at most
+  if (h.metric < ESG_METRIC_L2 || h.metric > ESG_METRIC_IP ||
+      h.dq != (h.metric == ESG_METRIC_IP ? h.d - 1 : h.d) || h.dq < 1 ||
+      !(h.max_norm2 >= 0.0 && h.max_norm2 <= 1e300) ||
+      (h.metric != ESG_METRIC_IP && h.max_norm2 != 0.0))
+    return ESG_EFORMAT;
   // rows per depth: the tree's depths cover all n positions; the chains'
   // depths only their own prefix or suffix
   std::vector<int64_t> row_base((size_t)h.n_depth);
@@ -398,7 +424,7 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
 
   const esgk::KernelTable* kt = nullptr;
   for (const auto& t : kernel_tables())
-    if (t.dim == h.d) kt = &t;
+    if (!kt && same_shape(h.d, t.dim)) kt = &t;
   if (!kt) return ESG_EUNSUPPORTED;
 
   std::vector<int64_t> ids((size_t)h.n);
@@ -438,6 +464,9 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
   ix->c_den = h.c_den;
   ix->fanout = h.fanout;
   ix->layout = h.layout;
+  ix->metric = h.metric;
+  ix->dq = h.dq;
+  ix->max_norm2 = h.max_norm2;
   ix->kt = kt;
   if (hipDeviceGetAttribute(&ix->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device) !=
       hipSuccess) {
@@ -542,6 +571,9 @@ int32_t esg_index_info(const esg_index* idx, esg_index_info_t* out) {
   out->has_bf16 = idx->vec16 != nullptr;
   out->has_fp8 = idx->vec8 != nullptr;
   out->device_bytes = idx->device_bytes;
+  out->metric = idx->metric;
+  out->dq = idx->dq;
+  out->max_norm2 = idx->max_norm2;
   return ESG_OK;
 }
 
@@ -649,6 +681,7 @@ esgk::ScanArgs scan_args(esg_index* idx, const float* queries, const int64_t* l,
   S.ext_id = idx->ext_id;
   S.n = idx->n;
   S.d = idx->d;
+  S.dq = idx->dq;
   S.dp = idx->dp;
   S.queries = queries;
   S.l = l;
@@ -907,7 +940,7 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   if (o.visited && o.visited_cap < 1) return ESG_EINVAL;
   int32_t mr = 0;
   if (o.router_threshold > 0) {
-    if (!idx->vec16 || !idx->norm2) return ESG_EUNSUPPORTED;
+    if (!idx->vec16 || !idx->norm2 || !idx->kt->scan_select[0]) return ESG_EUNSUPPORTED;
     if (k > 128) return ESG_EINVAL;
     if (nq > idx->res_queries || nq > idx->res_windows / (1 << scan_width_index(k)))
       return ESG_ERANGE;
@@ -933,6 +966,7 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   a.ext_id = idx->ext_id;
   a.n = idx->n;
   a.d = idx->d;
+  a.dq = idx->dq;
   a.dp = idx->dp;
   a.R = idx->R;
   a.leaf = idx->leaf;

@@ -49,7 +49,8 @@ struct ScanArgs {
   const int64_t* ext_id;   // [n]
   int64_t n;
   int32_t d, dp;
-  const float* queries;    // [nq][d]
+  int32_t dq;              // values per query row (<= d; the rest of a query reads as 0)
+  const float* queries;    // [nq][dq]
   const int64_t* l;
   const int64_t* r;
   int64_t nq;
@@ -153,7 +154,8 @@ __global__ __launch_bounds__(256) void scan_select_kernel(ScanArgs S) {
   constexpr int CAP = 64 * E;                  // list length per window
   __shared__ __align__(16) uint16_t tile[TP * ROW];
   __shared__ float tnorm[TP];
-  __shared__ uint32_t buf[4][kScanWinPerWave][kScanBuf];
+  constexpr int BUF = DP >= 1024 ? 96 : kScanBuf;   // keeps the LDS footprint under 64 KB
+  __shared__ uint32_t buf[4][kScanWinPerWave][BUF];
   __shared__ int32_t cnt[4][kScanWinPerWave];
   __shared__ int64_t span[4][2];
   const int lane = lane_id();
@@ -170,14 +172,14 @@ __global__ __launch_bounds__(256) void scan_select_kernel(ScanArgs S) {
   const int64_t ws = wvalid ? S.win_s[wid] : 0, we = wvalid ? S.win_e[wid] : -1;
   // query operand (B): bfloat16 of q[32c + 8*grp .. +7]; |q|^2 in float32
   bf16x8_t qb[NK];
-  const float* q = S.queries + (int64_t)qid * S.d;
+  const float* q = S.queries + (int64_t)qid * S.dq;
   float qn = 0.0f;
 #pragma unroll
   for (int c = 0; c < NK; c++) {
 #pragma unroll
     for (int e = 0; e < 8; e++) {
       const int j = 32 * c + 8 * grp + e;
-      const float v = (wvalid && j < S.d) ? q[j] : 0.0f;
+      const float v = (wvalid && j < S.dq) ? q[j] : 0.0f;
       qb[c][e] = __builtin_bit_cast(__bf16, f32_to_bf16_rne(v));
       qn = __builtin_fmaf(v, v, qn);
     }
@@ -245,8 +247,8 @@ __global__ __launch_bounds__(256) void scan_select_kernel(ScanArgs S) {
     for (int u = (int)threadIdx.x; u < TP * CH; u += 256) {
       const int row = u / CH, ch = u % CH;
       const int64_t p = t0 + row;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (p < S.n) v = *reinterpret_cast<const uint4*>(S.vec16 + p * S.dp + ch * 8);
+      uint4 v = make_uint4(0, 0, 0, 0);   // chunks past the index's row stay zero
+      if (p < S.n && ch * 8 < S.dp) v = *reinterpret_cast<const uint4*>(S.vec16 + p * S.dp + ch * 8);
       *reinterpret_cast<uint4*>(&tile[row * ROW + ch * 8]) = v;
     }
     if (threadIdx.x < TP) {
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(256) void scan_select_kernel(ScanArgs S) {
     __syncthreads();                           // buffer counts complete, tile reusable
     // windows whose buffer could overflow during the next tile are merged now
     const uint32_t need =
-        (uint32_t)ballot(lane < kScanWinPerWave && cnt[wave][lane] > kScanBuf - TP) & 0xFFFFu;
+        (uint32_t)ballot(lane < kScanWinPerWave && cnt[wave][lane] > BUF - TP) & 0xFFFFu;
     if (need) flush(need);
   }
   const uint32_t rest = (uint32_t)ballot(lane < kScanWinPerWave && cnt[wave][lane] > 0) & 0xFFFFu;
@@ -338,12 +340,13 @@ __global__ __launch_bounds__(256) void rerank_kernel(ScanArgs S) {
   }
   // float32 rerank of the first mr candidates
   const int mr = S.mr;
-  const float* q = S.queries + (int64_t)qi * S.d;
+  const float* q = S.queries + (int64_t)qi * S.dq;
   float qr32[CPL32][4];
-  load_query<kF32, G32, CPL32>(q, S.d, lane, qr32);
+  load_query<kF32, G32, CPL32>(q, S.dq, lane, qr32);
   SearchArgs A;
   A.vec = S.vec;
   A.d = S.d;
+  A.dq = S.dq;
   A.dp = S.dp;
   const int k = S.k;
   uint64_t R[E];
@@ -374,7 +377,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(ScanArgs S) {
     // |approx - exact| <= 2 (dx + dq + dx dq) |x||q|            (bfloat16 rounding)
     //                    + gamma (2 |x||q| (1+dx)(1+dq) + |x|^2 + |q|^2)  (float32 sums)
     float qn = 0.0f, dq = 0.0f;
-    for (int j = lane; j < S.d; j += kWave) {
+    for (int j = lane; j < S.dq; j += kWave) {
       const float v = q[j];
       qn = __builtin_fmaf(v, v, qn);
       const float vb = __uint_as_float((uint32_t)f32_to_bf16_rne(v) << 16);
@@ -435,13 +438,14 @@ __global__ __launch_bounds__(256) void fallback_window_kernel(ScanArgs S) {
   SearchArgs A;
   A.vec = S.vec;
   A.d = S.d;
+  A.dq = S.dq;
   A.dp = S.dp;
   for (int64_t t = 0; t < nfb; t++) {
     const int32_t qi = S.fb_list[t];
     const int64_t w0 = S.q_win0[qi], nwq = S.q_nwin[qi];
     if (gw >= nwq) continue;
     float qr32[CPL32][4];
-    load_query<kF32, G32, CPL32>(S.queries + (int64_t)qi * S.d, S.d, lane, qr32);
+    load_query<kF32, G32, CPL32>(S.queries + (int64_t)qi * S.dq, S.dq, lane, qr32);
     for (int64_t j = gw; j < nwq; j += nwaves) {
       Part pt;
       pt.x = (uint32_t)S.win_s[w0 + j];

@@ -50,11 +50,14 @@ constexpr int kDp = (ESG_DIM + 15) / 16 * 16;
 constexpr int kNK = (kDp + 31) / 32;
 // positions per LDS tile of the scan: the staged tile stays within 32 KB
 constexpr int kTP = kDp <= 128 ? 64 : (kDp <= 256 ? 32 : 16);
+// the scan stages a tile of kTP rows in LDS: compiled up to rows of 1,024
+constexpr bool kHasScan = kDp <= 1024;
 
 template <int E>
 void fill_scan(KernelTable* t, int slot) {
   using S32 = Shape<kF32>;
-  t->scan_select[slot] = reinterpret_cast<const void*>(&scan_select_kernel<kNK, E, kTP, kDp>);
+  if constexpr (kHasScan)
+    t->scan_select[slot] = reinterpret_cast<const void*>(&scan_select_kernel<kNK, E, kTP, kDp>);
   t->rerank[slot] = reinterpret_cast<const void*>(&rerank_kernel<S32::G, S32::CPL, E>);
   t->fallback[slot] = reinterpret_cast<const void*>(&fallback_window_kernel<S32::G, S32::CPL, E>);
   t->fb_merge[slot] = reinterpret_cast<const void*>(&fallback_merge_kernel<E>);

@@ -380,9 +380,9 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
     return;
   }
 
-  const float* q = A.queries + qi * (int64_t)A.d;
+  const float* q = A.queries + qi * (int64_t)A.dq;
   float qr[CPL][Traits<KIND>::W];
-  load_query<KIND, G, CPL>(q, A.d, lane, qr);
+  load_query<KIND, G, CPL>(q, A.dq, lane, qr);
 
   const int m = A.ef;
   const int cap_p = A.cand_cap;
@@ -399,7 +399,7 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
       if constexpr (KIND == kF32) scan_leaf<G, CPL, E>(A, Ls, pt, k, qr, Qp, lane);
       else {
         float qr32[CPL32][4];               // loaded where needed, not kept across the search
-        load_query<kF32, G32, CPL32>(q, A.d, lane, qr32);
+        load_query<kF32, G32, CPL32>(q, A.dq, lane, qr32);
         scan_leaf<G32, CPL32, E>(A, Ls, pt, k, qr32, Qp, lane);
       }
       st.n_visited = (int64_t)(pt.y - pt.x) + 1;
@@ -413,7 +413,7 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
       if constexpr (KIND != kF32)
         if (A.rerank) {
           float qr32[CPL32][4];
-          load_query<kF32, G32, CPL32>(q, A.d, lane, qr32);
+          load_query<kF32, G32, CPL32>(q, A.dq, lane, qr32);
           rerank_f32<G32, CPL32, E>(A, Ls, k, qr32, Qp, lane);
         }
 #pragma unroll

@@ -31,6 +31,7 @@ import math
 import numpy as np
 
 __all__ = ["Workload", "WORKLOADS", "make_workload", "fixed_width_ranges", "half_bounded_ranges",
+           "spread_norms",
            "sha256_of"]
 
 
@@ -172,6 +173,16 @@ def half_bounded_ranges(n: int, nq: int, lo: float, seed: int):
     l = np.where(pre, 0, n - width).astype(np.int64)
     r = np.where(pre, width - 1, n - 1).astype(np.int64)
     return l, r
+
+
+def spread_norms(X: np.ndarray, sigma: float, seed: int) -> np.ndarray:
+    """Rows of X rescaled by exp(sigma z), z standard normal per row: the
+    log-normal spread of norms of inner-product workloads (for instance
+    recommendation embeddings), where the largest inner product and the
+    nearest point differ."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = np.exp(sigma * rng.standard_normal(X.shape[0]))
+    return (X.astype(np.float64) * s[:, None]).astype(np.float32)
 
 
 def sha256_of(*arrays: np.ndarray) -> str:

@@ -87,7 +87,7 @@ def oracle_scan(oix, Q, l, r, k):
         od = np.zeros(k, np.float32)
         op = np.zeros(k, np.int64)
         ol = np.zeros(1, np.int32)
-        q = np.ascontiguousarray(Q[i], np.float32)
+        q = oix.stored_query(Q[i])
         st = L.oracle_scan_part(oix.cstruct(), int(l[i]), int(r[i]), q.ctypes.data, k,
                                 od.ctypes.data, op.ctypes.data, ol.ctypes.data)
         assert st == 0

@@ -3,6 +3,7 @@ strings, the index builder's output structure and determinism, and the
 loader's rejection of malformed files."""
 from __future__ import annotations
 
+import ctypes
 import os
 import re
 import shutil
@@ -258,7 +259,82 @@ def test_loader_rejects_malformed(small_index, tmp_path):
     bad = raw.copy()
     assert struct.unpack_from("<i", bad, 44)[0] == 2        # c_den
     struct.pack_into("<i", bad, 44, 1)
-    struct.pack_into("<I", bad, 124, _crc32c(bytes(bad[:124])))
+    struct.pack_into("<I", bad, 140, _crc32c(bytes(bad[:140])))
     assert variant("cden", bad) == esg.ESG_EFORMAT
+    # metric fields (offset 124: metric, dq; 132: M^2) that disagree with
+    # each other or with d, each behind a valid checksum
+    assert struct.unpack_from("<2i", raw, 124) == (0, struct.unpack_from("<i", raw, 24)[0])
+    d = struct.unpack_from("<i", raw, 24)[0]
+    for name, metric, dq, m2 in [("metric", 3, d, 0.0), ("ip_dq", 2, d, 1.0),
+                                 ("l2_m2", 0, d, 1.0), ("ang_dq", 1, d - 1, 0.0),
+                                 ("ip_nan", 2, d - 1, float("nan"))]:
+        bad = raw.copy()
+        struct.pack_into("<2id", bad, 124, metric, dq, m2)
+        struct.pack_into("<I", bad, 140, _crc32c(bytes(bad[:140])))
+        assert variant(name, bad) == esg.ESG_EFORMAT, name
     # a well-formed file: loads where a device exists, reports the missing device here
     assert _load_status(path) in (esg.ESG_OK, esg.ESG_EHIP)
+
+
+@pytest.fixture(scope="module", params=["ip", "angular"])
+def metric_index(request, tmp_path_factory):
+    m = request.param
+    w = synth.make_workload(0, n=3000, nq=80)
+    X = synth.spread_norms(w["X"], 0.5, 11)
+    path = str(tmp_path_factory.mktemp(f"cabi_{m}") / "s.esgi")
+    esg.build_index(X, w["attr"].astype(np.float64), path, degree=12, leaf=100,
+                    ef_construction=64, metric=m)
+    return w, X, path, {"ip": oracle.METRIC_IP, "angular": oracle.METRIC_ANGULAR}[m]
+
+
+def test_metric_builder_stores_transform(metric_index):
+    """The stored rows are the float64 transform rounded to float32 (unit
+    rows; [x, sqrt(M^2 - |x|^2)]), in position order; the header carries the
+    metric, the query length and M^2."""
+    w, X, path, metric = metric_index
+    ix = oracle.read_index(path)
+    S, m2 = oracle.metric_store64(X, metric)
+    assert ix.metric == metric and ix.d == S.shape[1]
+    assert ix.dq == X.shape[1]
+    assert ix.max_norm2 == pytest.approx(m2, rel=1e-13, abs=0)
+    want = S[ix.ext_id].astype(np.float32)
+    assert np.allclose(ix.vec, want, rtol=2e-7, atol=1e-6 * np.sqrt(max(m2, 1.0)))
+
+
+def test_metric_index_oracle_recall(metric_index):
+    """End to end on the CPU: the oracle's Alg. 4 + Alg. 1 search over the
+    stored rows with dq-long queries finds the exact top 10 of the metric
+    (largest inner product, or cosine) over the original rows."""
+    w, X, path, metric = metric_index
+    ix = oracle.read_index(path)
+    Q, l, r = w["Q"], w["l"], w["r"]
+    ids, _, st = oracle.query_batch(ix, Q, l, r, 10, 128)
+    assert np.all(st == 0)
+    pos_of = np.empty(ix.n, np.int64)
+    pos_of[ix.ext_id] = np.arange(ix.n)
+    Xpos = X[ix.ext_id]
+    gt, _ = oracle.exact_metric(Xpos, Q, l, r, 10, metric)
+    hit = 0
+    tot = 0
+    for i in range(len(Q)):
+        g = gt[i][gt[i] >= 0]
+        f = pos_of[ids[i][ids[i] >= 0]]
+        hit += len(np.intersect1d(g, f))
+        tot += len(g)
+    assert hit / tot >= 0.95
+
+
+def test_metric_builder_errors(tmp_path):
+    X = np.ones((10, 4), np.float32)
+    X[3] = 0
+    with pytest.raises(esg.EsgError) as e:      # a zero row has no direction
+        esg.build_index(X, np.arange(10.0), str(tmp_path / "x"), metric="angular")
+    assert e.value.status == esg.ESG_EINVAL
+    X[3] = np.inf
+    with pytest.raises(esg.EsgError) as e:
+        esg.build_index(X, np.arange(10.0), str(tmp_path / "x"), metric="ip")
+    assert e.value.status == esg.ESG_EINVAL
+    p = esg.BuildParams(16, 4, 16, 2, 1, 0, 0, 0, 7)
+    st = esg.lib().esg_build_index(X.ctypes.data, np.arange(10.0).ctypes.data, 10, 4,
+                                   ctypes.byref(p), str(tmp_path / "y").encode())
+    assert st == esg.ESG_EINVAL

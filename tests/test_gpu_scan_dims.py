@@ -1,8 +1,8 @@
 """GPU parity of the MFMA brute-force scan at the dimensions it serves.
 
 The scan forms bfloat16 dot products over 32-wide K chunks (d = 64, 96,
-128, 768 take 2, 3, 4 and 24 chunks), and its certificate bound grows with
-d.  At each of these dimensions, for range widths from 1 point to the whole
+100, 128, 768, 1024 take 2, 3, 4, 4, 24 and 32 chunks), and its certificate
+bound grows with d.  At each of these dimensions, for range widths from 1 point to the whole
 set (many 2,048-position windows), its answer must equal the oracle's
 float32 scan of [l,r] bit for bit, whether a query was certified or
 rescanned exactly (and with every query forced through the exact path).
@@ -30,8 +30,11 @@ DEV = torch.device("cuda:0")
 NQ = 240
 
 # (workload law, d, N): DEEP-shaped unit-norm at d = 64 and 96, SIFT-shaped
-# uint8-valued at d = 128, embedding-shaped unit-norm at d = 768.
-SHAPES = [(2, 64, 20000), (2, 96, 20000), (1, 128, 20000), (3, 768, 6000)]
+# uint8-valued at d = 128, embedding-shaped unit-norm at d = 768 and 1024,
+# and GLOVE's d = 100, served by the kernels compiled for 128 (rows of 112
+# values, the tile's last K chunk half empty).
+SHAPES = [(2, 64, 20000), (2, 96, 20000), (2, 100, 20000), (1, 128, 20000), (3, 768, 6000),
+          (3, 1024, 4000)]
 
 
 def _t(a):
