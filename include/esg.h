@@ -147,6 +147,24 @@ typedef struct {
 int32_t esg_build_index(const float* vecs, const double* attr, int64_t n, int32_t d,
                         const esg_build_params* params, const char* out_path);
 
+/* The same build with the insertion rounds on HIP device `hip_device`: for
+ * each round (the batches of every node of one depth, inserted against the
+ * graphs as they were before the round), the beam searches run in the
+ * search kernel, and the occlusion pruning and the reverse edges (grouped
+ * per target) in kernels of their own; distances use the float32
+ * summation order of the search kernels on both paths.  Entry points
+ * (medoids in float64) and the reachability repair stay on the host
+ * between depths.  Writes the same file as esg_build_index for the same
+ * inputs and parameters.  Needs batch_max <= 65536 and a dimension with
+ * compiled kernels.  Device memory: the vectors (4 n d bytes), every
+ * depth's rows (4 n R n_depth), the search workspace of a loaded index,
+ * and buffers for rounds of up to 65,536 points.
+ * Errors: those of esg_build_index, plus EUNSUPPORTED (dimension),
+ * EHIP. */
+int32_t esg_build_index_gpu(const float* vecs, const double* attr, int64_t n, int32_t d,
+                            const esg_build_params* params, int32_t hip_device,
+                            const char* out_path);
+
 /* ---- loaded index -------------------------------------------------------- */
 typedef struct esg_index esg_index;
 

@@ -91,6 +91,7 @@ _lib = None
 _I32, _I64, _VP, _CP = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_char_p
 SIGNATURES = {
     "esg_build_index": (_I32, [_VP, _VP, _I64, _I32, _VP, _CP]),
+    "esg_build_index_gpu": (_I32, [_VP, _VP, _I64, _I32, _VP, _I32, _CP]),
     "esg_load_index": (_I32, [_CP, _I32, _VP]),
     "esg_index_add_storage": (_I32, [_VP, _I32, _VP]),
     "esg_index_info": (_I32, [_VP, _VP]),
@@ -138,8 +139,10 @@ def _check(status: int, what: str):
 def build_index(X: np.ndarray, attr: np.ndarray, path: str, degree: int = 16, leaf: int = 1024,
                 ef_construction: int = 200, threads: int = 0, batch_max: int = 0,
                 verbose: bool = False, fanout: int = 2, layout: str = "tree",
-                metric: str = "l2") -> None:
-    """esg_build_index: host build of the index file -- layout "tree": the
+                metric: str = "l2", device: int | None = None) -> None:
+    """esg_build_index (host threads) or, with a HIP `device`,
+    esg_build_index_gpu (insertion rounds on that device; the same file
+    byte for byte): the index file -- layout "tree": the
     HBI-2D segment tree (Alg. 3) of the given fanout (elastic constant
     1/fanout); layout "chain": the half-bounded HBI-1D index (Alg. 2),
     prefix and suffix graphs of sizes N, ceil(N/B), ... with B = fanout.
@@ -151,9 +154,14 @@ def build_index(X: np.ndarray, attr: np.ndarray, path: str, degree: int = 16, le
         raise ValueError("X must be [n,d] and attr [n]")
     p = BuildParams(degree, leaf, ef_construction, fanout, threads, batch_max, int(verbose),
                     {"tree": 0, "chain": 1}[layout], METRICS[metric])
-    st = lib().esg_build_index(X.ctypes.data, attr.ctypes.data, X.shape[0], X.shape[1],
-                               ctypes.byref(p), path.encode())
-    _check(st, "esg_build_index")
+    if device is None:
+        st = lib().esg_build_index(X.ctypes.data, attr.ctypes.data, X.shape[0], X.shape[1],
+                                   ctypes.byref(p), path.encode())
+        _check(st, "esg_build_index")
+    else:
+        st = lib().esg_build_index_gpu(X.ctypes.data, attr.ctypes.data, X.shape[0], X.shape[1],
+                                       ctypes.byref(p), int(device), path.encode())
+        _check(st, "esg_build_index_gpu")
 
 
 def _stream_ptr(stream):

@@ -37,26 +37,37 @@
 
 #include "../../include/esg.h"
 #include "esg_format.h"
+#include "esg_gpu_build.h"
 
 namespace {
 
 using Cand = std::pair<float, uint32_t>;  // (squared distance, position)
 
-inline float l2sq(const float* a, const float* b, int d) {
-  float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int j = 0;
-  for (; j + 8 <= d; j += 8) {
-    for (int e = 0; e < 8; e++) {
-      float t = a[j + e] - b[j + e];
-      acc[e] += t * t;
+// Squared Euclidean distance in float32 with the search kernels' fixed
+// summation order, so that the host and the device builders compute the
+// same values: the row is cut into chunks of 4 values, chunk c goes to lane
+// c mod G (G = the chunk count rounded up to a power of two, at most 64),
+// each lane accumulates fma(x - q, x - q, acc) over its chunks in order,
+// and the lanes are added pairwise (lane t + lane t + s for s = 1, 2, 4, ...).
+inline float l2sq(const float* x, const float* q, int d) {
+  const int C = (d + 3) / 4;
+  int G = 1;
+  while (G < C) G <<= 1;
+  if (G > 64) G = 64;
+  float acc[64];
+  for (int t = 0; t < G; t++) acc[t] = 0.0f;
+  for (int c = 0; c < C; c++) {
+    float a = acc[c & (G - 1)];
+    const int j0 = 4 * c, j1 = std::min(d, j0 + 4);
+    for (int j = j0; j < j1; j++) {
+      const float t = x[j] - q[j];
+      a = std::fma(t, t, a);
     }
+    acc[c & (G - 1)] = a;
   }
-  float s = 0.f;
-  for (; j < d; j++) {
-    float t = a[j] - b[j];
-    s += t * t;
-  }
-  return s + ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  for (int s = 1; s < G; s <<= 1)
+    for (int t = 0; t < G; t += 2 * s) acc[t] = acc[t] + acc[t + s];
+  return acc[0];
 }
 
 struct VisitTags {
@@ -77,11 +88,22 @@ struct VisitTags {
 // First position of child j of the node starting at a with L points.
 inline int64_t child_start(int64_t a, int64_t L, int f, int64_t j) { return a + (j * L + f - 1) / f; }
 
+// One insertion sequence: the graph on positions [a, cur-1] receives
+// positions cur..end, then next_cur..next_end (a node whose first child is
+// built from scratch inserts that child's points first).
+struct Job {
+  int64_t a = 0, cur = 0, end = -1, next_cur = 0, next_end = -1;
+  uint32_t ep = 0;
+  int64_t ep_size = 0;
+};
+
 struct Builder {
   int64_t n;
   int d, R, leaf, efc, batch_max, n_depth, verbose, fanout;
   const float* X;          // [n][d], position order
   uint32_t* adj;           // [n_depth][n][R]
+  esgb::GpuState* gpu = nullptr;   // insertion rounds on a HIP device (null: host threads)
+  bool gpu_ok = true;
 
   uint32_t* rows(int t) { return adj + (size_t)t * (size_t)n * (size_t)R; }
   const float* vec(uint32_t p) const { return X + (size_t)p * (size_t)d; }
@@ -146,96 +168,155 @@ struct Builder {
     return m;
   }
 
+  // Every sum runs in point order (per dimension) or dimension order (per
+  // point), whatever the thread count, so the result does not depend on it.
   uint32_t medoid(int64_t a, int64_t b) const {
+    const int64_t L = b - a + 1;
+    const bool par = L * d >= (1 << 20);
     std::vector<double> mean((size_t)d, 0.0);
-    for (int64_t p = a; p <= b; p++)
-      for (int j = 0; j < d; j++) mean[j] += (double)X[(size_t)p * d + j];
-    for (int j = 0; j < d; j++) mean[j] /= (double)(b - a + 1);
+    constexpr int kCols = 16;
+#pragma omp parallel for schedule(static) if (par)
+    for (int j0 = 0; j0 < d; j0 += kCols) {
+      const int j1 = std::min(d, j0 + kCols);
+      double acc[kCols] = {};
+      for (int64_t p = a; p <= b; p++)
+        for (int j = j0; j < j1; j++) acc[j - j0] += (double)X[(size_t)p * d + j];
+      for (int j = j0; j < j1; j++) mean[(size_t)j] = acc[j - j0] / (double)L;
+    }
     double best = INFINITY;
     uint32_t arg = (uint32_t)a;
-    for (int64_t p = a; p <= b; p++) {
-      double s = 0.0;
-      for (int j = 0; j < d; j++) {
-        double t = (double)X[(size_t)p * d + j] - mean[j];
-        s += t * t;
+#pragma omp parallel if (par)
+    {
+      double tb = INFINITY;
+      uint32_t ta = (uint32_t)a;
+#pragma omp for schedule(static) nowait
+      for (int64_t p = a; p <= b; p++) {
+        double s = 0.0;
+        for (int j = 0; j < d; j++) {
+          const double t = (double)X[(size_t)p * d + j] - mean[(size_t)j];
+          s += t * t;
+        }
+        if (s < tb) {   // static chunks in order: the first minimum of the chunk
+          tb = s;
+          ta = (uint32_t)p;
+        }
       }
-      if (s < best) {
-        best = s;
-        arg = (uint32_t)p;
+#pragma omp critical
+      if (tb < best || (tb == best && ta < arg)) {
+        best = tb;
+        arg = ta;
       }
     }
     return arg;
   }
 
-  // Graph on [a, s-1] (rows of `rw`) receives positions s..e.
-  void insert_range(uint32_t* rw, int64_t a, int64_t s, int64_t e, bool par) {
-    int64_t cur = s;
-    int64_t ep_size = 0;
-    uint32_t ep = (uint32_t)a;
-    std::vector<std::vector<uint32_t>> sel;
-    std::vector<std::pair<uint64_t, float>> prop;  // ((target<<32)|source, dist)
-    while (cur <= e) {
-      int64_t size = cur - a;
-      if (size >= 2 * ep_size + 1 || ep_size == 0) {
-        ep = medoid(a, cur - 1);
-        ep_size = size;
+  // One insertion round against the frozen graph: every point pts[i] is
+  // searched from eps[i] and pruned to at most R neighbours (all in
+  // parallel), then the forward rows are written and the reverse edges
+  // applied, one target at a time in (target, source) order.
+  void round_cpu(uint32_t* rw, const std::vector<uint32_t>& pts, const std::vector<uint32_t>& eps) {
+    const int64_t nb = (int64_t)pts.size();
+    std::vector<uint32_t> sel((size_t)nb * R, ESG_NO_NODE);
+#pragma omp parallel for schedule(dynamic, 1) if (nb > 1)
+    for (int64_t i = 0; i < nb; i++) {
+      // One visit-tag array per OS thread (nested regions run serialized).
+      static thread_local VisitTags vt;
+      static thread_local std::vector<Cand> cands;
+      if ((int64_t)vt.tag.size() != n) vt.reset(n);
+      search(rw, eps[(size_t)i], vec(pts[(size_t)i]), efc, vt, cands);
+      occlude(cands, pts[(size_t)i], &sel[(size_t)i * R]);
+    }
+    std::vector<uint64_t> prop;   // (target << 32) | source
+    for (int64_t i = 0; i < nb; i++) {
+      const uint32_t p = pts[(size_t)i];
+      std::memcpy(rw + (size_t)p * R, &sel[(size_t)i * R], sizeof(uint32_t) * R);
+      for (int j = 0; j < R; j++) {
+        const uint32_t c = sel[(size_t)i * R + j];
+        if (c == ESG_NO_NODE) break;
+        prop.push_back(((uint64_t)c << 32) | p);
       }
-      int64_t B = std::max<int64_t>(1, std::min<int64_t>(size / 16, batch_max));
-      B = std::min<int64_t>(B, e - cur + 1);
-      sel.assign((size_t)B, std::vector<uint32_t>((size_t)R, ESG_NO_NODE));
-      // 1) searches against the frozen graph
-#pragma omp parallel for schedule(dynamic, 1) if (par && B > 1)
-      for (int64_t i = 0; i < B; i++) {
-        std::vector<Cand> cands;
-        uint32_t p = (uint32_t)(cur + i);
-        // One visit-tag array per OS thread: omp_get_thread_num() is 0 inside
-        // the serialized inner region of every outer thread, so it cannot
-        // index per-thread state here.
-        static thread_local VisitTags vt;
-        if ((int64_t)vt.tag.size() != n) vt.reset(n);
-        search(rw, ep, vec(p), efc, vt, cands);
-        occlude(cands, p, sel[(size_t)i].data());
+    }
+    std::sort(prop.begin(), prop.end());
+    std::vector<size_t> starts;
+    for (size_t i = 0; i < prop.size(); i++)
+      if (i == 0 || (prop[i] >> 32) != (prop[i - 1] >> 32)) starts.push_back(i);
+    starts.push_back(prop.size());
+    const int64_t n_groups = (int64_t)starts.size() - 1;
+#pragma omp parallel for schedule(dynamic, 16) if (n_groups > 64)
+    for (int64_t g = 0; g < n_groups; g++) {
+      const size_t i0 = starts[(size_t)g], i1 = starts[(size_t)g + 1];
+      const uint32_t c = (uint32_t)(prop[i0] >> 32);
+      uint32_t* row = rw + (size_t)c * R;
+      int len = row_len(row, R);
+      if (len + (int)(i1 - i0) <= R) {
+        for (size_t i = i0; i < i1; i++) row[len++] = (uint32_t)prop[i];
+        continue;
       }
-      // 2) forward edges and reverse-edge proposals, in position order
-      prop.clear();
-      for (int64_t i = 0; i < B; i++) {
-        uint32_t p = (uint32_t)(cur + i);
-        std::memcpy(rw + (size_t)p * R, sel[(size_t)i].data(), sizeof(uint32_t) * R);
-        for (int j = 0; j < R; j++) {
-          uint32_t c = sel[(size_t)i][(size_t)j];
-          if (c == ESG_NO_NODE) break;
-          prop.push_back({((uint64_t)c << 32) | p, 0.f});
+      std::vector<Cand> cands;
+      cands.reserve((size_t)len + (i1 - i0));
+      for (int j = 0; j < len; j++) cands.push_back({l2sq(vec(c), vec(row[j]), d), row[j]});
+      for (size_t i = i0; i < i1; i++) {
+        const uint32_t p = (uint32_t)prop[i];
+        cands.push_back({l2sq(vec(c), vec(p), d), p});
+      }
+      std::sort(cands.begin(), cands.end());
+      occlude(cands, c, row);
+    }
+  }
+
+  // Runs insertion sequences in lockstep rounds: in each round every
+  // unfinished job inserts its next batch, whose size depends only on the
+  // job's current graph size.  Jobs write disjoint rows, so each one ends
+  // as it would alone.  The entry point of a job's searches is the medoid
+  // of its current graph, refreshed whenever the graph has doubled.
+  void insert_jobs(int depth, uint32_t* rw, std::vector<Job>& jobs) {
+    std::vector<uint32_t> pts, eps, lo, hi;
+    for (;;) {
+      std::vector<size_t> act;
+      for (size_t j = 0; j < jobs.size(); j++) {
+        Job& J = jobs[j];
+        if (J.cur > J.end && J.next_cur <= J.next_end) {
+          J.cur = J.next_cur;
+          J.end = J.next_end;
+          J.next_end = J.next_cur - 1;
+          J.ep_size = 0;
+        }
+        if (J.cur <= J.end) act.push_back(j);
+      }
+      if (act.empty()) break;
+#pragma omp parallel for schedule(dynamic, 1) if (act.size() > 1)
+      for (size_t u = 0; u < act.size(); u++) {
+        Job& J = jobs[act[u]];
+        const int64_t size = J.cur - J.a;
+        if (size >= 2 * J.ep_size + 1 || J.ep_size == 0) {
+          J.ep = medoid(J.a, J.cur - 1);
+          J.ep_size = size;
         }
       }
-      std::sort(prop.begin(), prop.end());
-      // group boundaries per target
-      std::vector<size_t> starts;
-      for (size_t i = 0; i < prop.size(); i++)
-        if (i == 0 || (prop[i].first >> 32) != (prop[i - 1].first >> 32)) starts.push_back(i);
-      starts.push_back(prop.size());
-      // 3) reverse edges, one target per iteration (targets are distinct)
-      const int64_t n_groups = (int64_t)starts.size() - 1;
-#pragma omp parallel for schedule(dynamic, 16) if (par && n_groups > 64)
-      for (int64_t g = 0; g < n_groups; g++) {
-        size_t i0 = starts[(size_t)g], i1 = starts[(size_t)g + 1];
-        uint32_t c = (uint32_t)(prop[i0].first >> 32);
-        uint32_t* row = rw + (size_t)c * R;
-        int len = row_len(row, R);
-        if (len + (int)(i1 - i0) <= R) {
-          for (size_t i = i0; i < i1; i++) row[len++] = (uint32_t)(prop[i].first & 0xFFFFFFFFu);
-          continue;
+      pts.clear();
+      eps.clear();
+      lo.clear();
+      hi.clear();
+      for (size_t j : act) {
+        Job& J = jobs[j];
+        int64_t B = std::max<int64_t>(1, std::min<int64_t>((J.cur - J.a) / 16, batch_max));
+        B = std::min<int64_t>(B, J.end - J.cur + 1);
+        for (int64_t i = 0; i < B; i++) {
+          pts.push_back((uint32_t)(J.cur + i));
+          eps.push_back(J.ep);
+          lo.push_back((uint32_t)J.a);
+          hi.push_back((uint32_t)(J.cur - 1));
         }
-        std::vector<Cand> cands;
-        cands.reserve((size_t)len + (i1 - i0));
-        for (int j = 0; j < len; j++) cands.push_back({l2sq(vec(c), vec(row[j]), d), row[j]});
-        for (size_t i = i0; i < i1; i++) {
-          uint32_t p = (uint32_t)(prop[i].first & 0xFFFFFFFFu);
-          cands.push_back({l2sq(vec(c), vec(p), d), p});
-        }
-        std::sort(cands.begin(), cands.end());
-        occlude(cands, c, row);
+        J.cur += B;
       }
-      cur += B;
+      if (gpu) {
+        if (!gpu_ok) continue;
+        if (esgb::gpu_round(gpu, depth, (int64_t)pts.size(), pts.data(), eps.data(), lo.data(),
+                            hi.data()) != ESG_OK)
+          gpu_ok = false;
+      } else {
+        round_cpu(rw, pts, eps);
+      }
     }
   }
 
@@ -306,19 +387,30 @@ struct Builder {
     return added;
   }
 
-  void build_node(int t, int64_t a, int64_t b, bool par) {
+  // The insertion job of node [a,b] at depth t (Alg. 3): its first child's
+  // graph is copied from depth t+1 when that child owns one; otherwise the
+  // first child is built from scratch from its first point.  Then the
+  // remaining points are inserted.
+  Job node_job(int t, int64_t a, int64_t b) {
     const int64_t mid = child_start(a, b - a + 1, fanout, 1) - 1;   // end of the first child
-    uint32_t* rw = rows(t);
+    Job J;
+    J.a = a;
     if (mid - a >= leaf) {
-      // first child owns a graph at depth t+1: copy it
-      std::memcpy(rw + (size_t)a * R, rows(t + 1) + (size_t)a * R,
-                  sizeof(uint32_t) * (size_t)R * (size_t)(mid - a + 1));
+      if (gpu) {
+        if (gpu_ok && esgb::gpu_copy_rows(gpu, t, t + 1, a, mid - a + 1) != ESG_OK) gpu_ok = false;
+      } else {
+        std::memcpy(rows(t) + (size_t)a * R, rows(t + 1) + (size_t)a * R,
+                    sizeof(uint32_t) * (size_t)R * (size_t)(mid - a + 1));
+      }
+      J.cur = mid + 1;
+      J.end = b;
     } else {
-      // build the left half from scratch, starting from its first point
-      for (int j = 0; j < R; j++) rw[(size_t)a * R + j] = ESG_NO_NODE;
-      if (mid > a) insert_range(rw, a, a + 1, mid, par);
+      J.cur = a + 1;
+      J.end = mid;
+      J.next_cur = mid + 1;
+      J.next_end = b;
     }
-    insert_range(rw, a, mid + 1, b, par);
+    return J;
   }
 };
 
@@ -430,17 +522,20 @@ void build_chain(Builder& B, const std::vector<int64_t>& sizes, std::vector<uint
   eps.assign(k, ESG_NO_NODE);
   std::fill(W.begin(), W.end(), ESG_NO_NODE);
   B.adj = W.data();
+  if (B.gpu && B.gpu_ok && esgb::gpu_reset(B.gpu, B.X) != ESG_OK) B.gpu_ok = false;
   int64_t done = 0;                     // positions [0, done) inserted
   for (size_t j = k; j-- > 0;) {
     const int64_t s = sizes[j];
-    if (done == 0) {
-      if (s > 1) B.insert_range(W.data(), 0, 1, s - 1, true);
-    } else if (s > done) {
-      B.insert_range(W.data(), 0, done, s - 1, true);
-    }
+    std::vector<Job> jobs(1);
+    jobs[0].a = 0;
+    jobs[0].cur = done == 0 ? 1 : done;
+    jobs[0].end = s - 1;
+    B.insert_jobs(0, W.data(), jobs);
+    if (B.gpu && B.gpu_ok && esgb::gpu_get_rows(B.gpu, 0, W.data()) != ESG_OK) B.gpu_ok = false;
     done = s;
     const uint32_t e = B.medoid(0, s - 1);
     B.repair(0, 0, s - 1, e);
+    if (B.gpu && B.gpu_ok && esgb::gpu_put_rows(B.gpu, 0, W.data()) != ESG_OK) B.gpu_ok = false;
     eps[j] = e;
     snapshot(j, s);                     // record the graph of [0, s - 1] now
     if (B.verbose)
@@ -449,10 +544,21 @@ void build_chain(Builder& B, const std::vector<int64_t>& sizes, std::vector<uint
   }
 }
 
+// Owns the device state of a GPU build.
+struct GpuHolder {
+  esgb::GpuState* g = nullptr;
+  ~GpuHolder() {
+    if (g) esgb::gpu_close(g);
+  }
+};
+
+// Points of one device insertion round at most (a job's batch must fit).
+constexpr int64_t kGpuRound = 65536;
+
 int32_t build_chains(const float* X, const std::vector<int64_t>& order,
                      const std::vector<double>& sorted_attr, int64_t n, int32_t d,
                      const esg_build_params& P, int fanout, const MetricInfo& mi,
-                     const char* out_path) {
+                     const char* out_path, int32_t device) {
   const std::vector<int64_t> sizes = esg::chain_sizes(n, P.leaf, fanout);
   const size_t k = sizes.size();
   if (k == 0 || 2 * k > 40) return ESG_ERANGE;
@@ -467,6 +573,12 @@ int32_t build_chains(const float* X, const std::vector<int64_t>& order,
   B.n_depth = 1;
   B.verbose = P.verbose;
   B.fanout = fanout;
+  GpuHolder gh;
+  if (device >= 0) {
+    const int32_t st = esgb::gpu_open(device, X, n, d, R, 1, B.efc, kGpuRound, &gh.g);
+    if (st != ESG_OK) return st;
+    B.gpu = gh.g;
+  }
   std::vector<uint32_t> W((size_t)n * R), eps_p, eps_s;
   const std::vector<int64_t> row_base = esg::chain_row_base(n, sizes);
   std::vector<uint32_t> adj((size_t)esg::chain_rows(sizes) * R, ESG_NO_NODE);
@@ -494,14 +606,15 @@ int32_t build_chains(const float* X, const std::vector<int64_t>& order,
     ep[1 + i] = eps_p[i];
     ep[1 + k + i] = (uint32_t)(n - 1 - (int64_t)eps_s[i]);
   }
+  if (!B.gpu_ok) return ESG_EHIP;
   return write_index(out_path, n, d, P, fanout, (int)(2 * k), 1, mi, order.data(),
                      sorted_attr.data(), X, adj, ep);
 }
 
 }  // namespace
 
-extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_t n, int32_t d,
-                                   const esg_build_params* params, const char* out_path) {
+static int32_t build_impl(const float* vecs, const double* attr, int64_t n, int32_t d,
+                   const esg_build_params* params, int32_t device, const char* out_path) {
   if (!vecs || !attr || !params || !out_path || n <= 0 || n >= (int64_t)ESG_NO_NODE || d <= 0)
     return ESG_EINVAL;
   const esg_build_params& P = *params;
@@ -511,6 +624,7 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
     return ESG_EINVAL;
   const int fanout = P.fanout == 0 ? 2 : P.fanout;
   if (fanout > ESG_FANOUT_MAX) return ESG_EUNSUPPORTED;
+  if (device >= 0 && P.batch_max > kGpuRound) return ESG_EINVAL;
   for (int64_t i = 0; i < n; i++)
     if (std::isnan(attr[i])) return ESG_EINVAL;
   try {
@@ -562,7 +676,7 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
     }
 
     if (P.layout == 1)
-      return build_chains(X.data(), order, sorted_attr, n, ds, P, fanout, mi, out_path);
+      return build_chains(X.data(), order, sorted_attr, n, ds, P, fanout, mi, out_path, device);
     std::vector<NodeRef> nodes;
     collect(0, n - 1, 0, 1, P.leaf, fanout, nodes);
     int n_depth = 0;
@@ -582,20 +696,24 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
     B.X = X.data();
     std::vector<uint32_t> adj((size_t)n_depth * (size_t)n * (size_t)P.degree, ESG_NO_NODE);
     B.adj = adj.data();
+    GpuHolder gh;
+    if (device >= 0 && n_depth > 0) {
+      const int32_t st =
+          esgb::gpu_open(device, X.data(), n, ds, B.R, n_depth, B.efc, kGpuRound, &gh.g);
+      if (st != ESG_OK) return st;
+      B.gpu = gh.g;
+    }
 
     std::vector<uint32_t> ep((size_t)esg::ep_count(n_depth, fanout), ESG_NO_NODE);
     for (int t = n_depth - 1; t >= 0; t--) {
       std::vector<NodeRef> level;
       for (const NodeRef& nd : nodes)
         if (nd.depth == t) level.push_back(nd);
-      bool outer = (int64_t)level.size() >= 2 * (int64_t)nthreads;
-      if (outer) {
-#pragma omp parallel for schedule(dynamic, 1)
-        for (int64_t i = 0; i < (int64_t)level.size(); i++)
-          B.build_node(t, level[(size_t)i].a, level[(size_t)i].b, false);
-      } else {
-        for (const NodeRef& nd : level) B.build_node(t, nd.a, nd.b, true);
-      }
+      std::vector<Job> jobs;
+      for (const NodeRef& nd : level) jobs.push_back(B.node_job(t, nd.a, nd.b));
+      B.insert_jobs(t, B.rows(t), jobs);
+      if (B.gpu && B.gpu_ok && esgb::gpu_get_rows(B.gpu, t, B.rows(t)) != ESG_OK) B.gpu_ok = false;
+      if (!B.gpu_ok) return ESG_EHIP;
       int64_t repaired = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : repaired)
       for (int64_t i = 0; i < (int64_t)level.size(); i++) {
@@ -604,6 +722,7 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
         ep[(size_t)nd.heap] = e;
         repaired += B.repair(t, nd.a, nd.b, e);
       }
+      if (B.gpu && esgb::gpu_put_rows(B.gpu, t, B.rows(t)) != ESG_OK) return ESG_EHIP;
       if (P.verbose)
         fprintf(stderr, "[esg_build] depth %d: %zu graph nodes, %lld edges added for reachability\n",
                 t, level.size(), (long long)repaired);
@@ -616,4 +735,16 @@ extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_
   } catch (...) {
     return ESG_EINVAL;
   }
+}
+
+extern "C" int32_t esg_build_index(const float* vecs, const double* attr, int64_t n, int32_t d,
+                                   const esg_build_params* params, const char* out_path) {
+  return build_impl(vecs, attr, n, d, params, -1, out_path);
+}
+
+extern "C" int32_t esg_build_index_gpu(const float* vecs, const double* attr, int64_t n, int32_t d,
+                                       const esg_build_params* params, int32_t hip_device,
+                                       const char* out_path) {
+  if (hip_device < 0) return ESG_EINVAL;
+  return build_impl(vecs, attr, n, d, params, hip_device, out_path);
 }

@@ -45,6 +45,9 @@ struct SearchArgs {
   int32_t fanout;         // children per tree node (the chains' base in layout 1)
   int32_t layout;         // 0: segment tree; 1: prefix and suffix chains (half-bounded index)
   const int64_t* row_base;// [n_depth]: row of position p at depth t is adj + (row_base[t] + p) R
+  // builder's insertion searches: when `forced` is set, query i searches
+  // the graph at depth forced_depth on [l[i], r[i]] from ep[i] (no Alg. 4)
+  int32_t forced, forced_depth;
   // batch
   const float* queries;   // [nq][dq]
   const int64_t* l;

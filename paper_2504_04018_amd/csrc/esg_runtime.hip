@@ -13,6 +13,8 @@
 #include "esg_dispatch.h"
 #include "esg_format.h"
 #include "esg_kernels.h"
+#include "esg_build_impl.h"
+#include "esg_gpu_build.h"
 #include "esg_scan_impl.h"
 
 #define ESG_DECLARE_DIM(d) extern "C" void esg_register_dim_##d(esgk::KernelTable*);
@@ -1065,3 +1067,400 @@ int32_t esg_search_batch(esg_index* idx, const float* queries, const int64_t* l,
 }
 
 }  // extern "C"
+
+// ---- device side of the index builder --------------------------------------------------
+
+namespace {
+
+__global__ void identity_kernel(int64_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = i;
+}
+
+// Query rows of the round: the inserted points' own vectors.
+__global__ void build_gather_kernel(const float* __restrict__ vec, int64_t dp, int32_t d,
+                                    const uint32_t* __restrict__ pts, int64_t nb,
+                                    float* __restrict__ q) {
+  const int64_t total = nb * d;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / d, j = i % d;
+    q[i] = vec[(int64_t)pts[b] * dp + j];
+  }
+}
+
+// Reverse-edge proposals (target c <- source p) grouped by target without a
+// sort: count per target (the first proposal registers the target), give
+// each target a segment, then fill the segments.  Segment layout and the
+// order inside a segment depend on atomic order; the consumer sorts what
+// it uses, so the rows written do not.
+__global__ void build_count_kernel(const uint32_t* __restrict__ pts, int64_t nb,
+                                   const uint32_t* __restrict__ rows, int32_t R,
+                                   int32_t* __restrict__ cnt, int32_t* __restrict__ touched,
+                                   int32_t* __restrict__ counters) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb * R) return;
+  const uint32_t c = rows[(int64_t)pts[i / R] * R + i % R];
+  if (c == ESG_NO_NODE) return;
+  if (atomicAdd(&cnt[c], 1) == 0) touched[atomicAdd(&counters[0], 1)] = (int32_t)c;
+}
+
+__global__ void build_alloc_kernel(const int32_t* __restrict__ touched,
+                                   const int32_t* __restrict__ cnt, int32_t* __restrict__ start,
+                                   int32_t* __restrict__ fill, int32_t* __restrict__ counters,
+                                   int64_t bound) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= bound || u >= counters[0]) return;
+  const int32_t c = touched[u];
+  start[c] = atomicAdd(&counters[1], cnt[c]);
+  fill[c] = 0;
+}
+
+__global__ void build_fill_kernel(const uint32_t* __restrict__ pts, int64_t nb,
+                                  const uint32_t* __restrict__ rows, int32_t R,
+                                  const int32_t* __restrict__ start, int32_t* __restrict__ fill,
+                                  uint32_t* __restrict__ srcs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb * R) return;
+  const uint32_t p = pts[i / R];
+  const uint32_t c = rows[(int64_t)p * R + i % R];
+  if (c == ESG_NO_NODE) return;
+  srcs[start[c] + atomicAdd(&fill[c], 1)] = p;
+}
+
+__global__ void build_reset_kernel(int32_t* counters) {
+  counters[0] = 0;
+  counters[1] = 0;
+}
+
+}  // namespace
+
+namespace esgb {
+
+struct GpuState {
+  esg_index ix;                 // vectors, adjacency of every depth, search workspace
+  int32_t efc = 0, hash_cap = 0, max_lds = 0;
+  int64_t max_round = 0;
+  uint32_t* pts = nullptr;      // [max_round] round arrays
+  uint32_t* eps = nullptr;
+  int64_t* l = nullptr;
+  int64_t* r = nullptr;
+  float* qbuf = nullptr;        // [max_round][d]
+  int64_t* cid = nullptr;       // [max_round][efc]
+  float* cd = nullptr;
+  int32_t* cnt = nullptr;       // [n]
+  int32_t* start = nullptr;
+  int32_t* fill = nullptr;
+  int32_t* touched = nullptr;   // [max_round * R]
+  uint32_t* srcs = nullptr;
+  int32_t* counters = nullptr;  // [0] touched targets, [1] proposals placed
+  std::vector<uint32_t> h32;    // host staging
+  std::vector<int64_t> h64;
+};
+
+int32_t gpu_open(int32_t device, const float* X, int64_t n, int32_t d, int32_t R,
+                 int32_t n_depth, int32_t efc, int64_t max_round, GpuState** out) {
+  if (!out || !X || n < 1 || n >= (int64_t)ESG_NO_NODE || d < 1 || d > 65536 || R < 1 ||
+      R > ESG_DEGREE_MAX || n_depth < 1 || n_depth > 40 || efc < 1 || max_round < 1)
+    return ESG_EINVAL;
+  if (efc > ESG_EF_MAX) return ESG_EUNSUPPORTED;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess) {
+    (void)hipGetLastError();
+    return ESG_EHIP;
+  }
+  if (device < 0 || device >= ndev) return ESG_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return ESG_EHIP;
+  const esgk::KernelTable* kt = nullptr;
+  for (const auto& t : kernel_tables())
+    if (!kt && same_shape(d, t.dim)) kt = &t;
+  if (!kt || !kt->build_prune || !kt->fn[esgk::kF32][width_index(efc)][0]) return ESG_EUNSUPPORTED;
+  // the visited hash keeps the low bits of a node-local key: <= 12 spare bits
+  int kb = 0;
+  while (kb < 32 && ((int64_t)1 << kb) < n) kb++;
+  int hash_cap = kDefaultHashCap;
+  while (hash_cap < 16384 && kb - __builtin_ctz((unsigned)hash_cap) > 12) hash_cap *= 2;
+  if (kb - __builtin_ctz((unsigned)hash_cap) > 12) return ESG_ERANGE;
+
+  GpuState* g = new (std::nothrow) GpuState();
+  if (!g) return ESG_ENOMEM;
+  esg_index& ix = g->ix;
+  ix.device = device;
+  ix.n = n;
+  ix.d = d;
+  ix.dq = d;
+  ix.dp = (d + 15) / 16 * 16;
+  ix.R = R;
+  ix.leaf = 1;
+  ix.n_depth = n_depth;
+  ix.kt = kt;
+  g->efc = efc;
+  g->hash_cap = hash_cap;
+  g->max_round = max_round;
+  if (hipDeviceGetAttribute(&ix.cu_count, hipDeviceAttributeMultiprocessorCount, device) !=
+          hipSuccess ||
+      hipDeviceGetAttribute(&g->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+          hipSuccess) {
+    delete g;
+    return ESG_EHIP;
+  }
+  ix.spill_slots = (int64_t)ix.cu_count * 32;
+  ix.spill_words = ((n + 31) / 32 + 63) / 64 * 64;
+  int32_t st = ESG_OK;
+  auto A = [&](void** p, size_t b) {
+    if (st == ESG_OK) st = ix.alloc(p, b);
+  };
+  const size_t spill_bytes = (size_t)ix.spill_slots * (ix.spill_words + esgk::kSpillLog) * 4;
+  const size_t M = (size_t)max_round;
+  A((void**)&ix.vec, (size_t)n * ix.dp * 4);
+  A((void**)&ix.adj, (size_t)n_depth * n * R * 4);
+  A((void**)&ix.ext_id, (size_t)n * 8);
+  A((void**)&ix.spill, spill_bytes);
+  A((void**)&ix.counter, 256);
+  A((void**)&ix.row_base, (size_t)n_depth * 8);
+  A((void**)&g->pts, M * 4);
+  A((void**)&g->eps, M * 4);
+  A((void**)&g->l, M * 8);
+  A((void**)&g->r, M * 8);
+  A((void**)&g->qbuf, M * d * 4);
+  A((void**)&g->cid, M * efc * 8);
+  A((void**)&g->cd, M * efc * 4);
+  A((void**)&g->cnt, (size_t)n * 4);
+  A((void**)&g->start, (size_t)n * 4);
+  A((void**)&g->fill, (size_t)n * 4);
+  A((void**)&g->touched, M * R * 4);
+  A((void**)&g->srcs, M * R * 4);
+  A((void**)&g->counters, 8);
+  if (st != ESG_OK) {
+    ix.release();
+    delete g;
+    return st;
+  }
+  std::vector<int64_t> rb((size_t)n_depth);
+  for (int t = 0; t < n_depth; t++) rb[(size_t)t] = (int64_t)t * n;
+  identity_kernel<<<1024, 256>>>(ix.ext_id, n);
+  const bool ok = hipGetLastError() == hipSuccess &&
+                  hipMemcpy(ix.row_base, rb.data(), rb.size() * 8, hipMemcpyHostToDevice) ==
+                      hipSuccess &&
+                  hipMemset(ix.counter, 0, 256) == hipSuccess &&
+                  hipMemset(ix.spill, 0, spill_bytes) == hipSuccess &&
+                  hipMemset(g->cnt, 0, (size_t)n * 4) == hipSuccess &&
+                  hipDeviceSynchronize() == hipSuccess;
+  if (!ok || (st = gpu_reset(g, X)) != ESG_OK) {
+    (void)hipGetLastError();
+    ix.release();
+    delete g;
+    return st != ESG_OK ? st : ESG_EHIP;
+  }
+  *out = g;
+  return ESG_OK;
+}
+
+int32_t gpu_reset(GpuState* g, const float* X) {
+  if (!g || !X) return ESG_EINVAL;
+  esg_index& ix = g->ix;
+  if (hipSetDevice(ix.device) != hipSuccess) return ESG_EHIP;
+  const bool ok =
+      hipDeviceSynchronize() == hipSuccess &&
+      hipMemset(ix.vec, 0, (size_t)ix.n * ix.dp * 4) == hipSuccess &&
+      hipMemcpy2D(ix.vec, (size_t)ix.dp * 4, X, (size_t)ix.d * 4, (size_t)ix.d * 4, (size_t)ix.n,
+                  hipMemcpyHostToDevice) == hipSuccess &&
+      hipMemset(ix.adj, 0xFF, (size_t)ix.n_depth * ix.n * ix.R * 4) == hipSuccess &&   // ESG_NO_NODE
+      hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    return ESG_EHIP;
+  }
+  return ESG_OK;
+}
+
+int32_t gpu_copy_rows(GpuState* g, int32_t dst, int32_t src, int64_t a, int64_t count) {
+  if (!g) return ESG_EINVAL;
+  esg_index& ix = g->ix;
+  if (dst < 0 || src < 0 || dst >= ix.n_depth || src >= ix.n_depth || a < 0 || count < 0 ||
+      a + count > ix.n)
+    return ESG_EINVAL;
+  if (hipSetDevice(ix.device) != hipSuccess) return ESG_EHIP;
+  const size_t row = (size_t)ix.R;
+  if (hipMemcpy(ix.adj + ((size_t)dst * ix.n + a) * row, ix.adj + ((size_t)src * ix.n + a) * row,
+                (size_t)count * row * 4, hipMemcpyDeviceToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    return ESG_EHIP;
+  }
+  return ESG_OK;
+}
+
+int32_t gpu_get_rows(GpuState* g, int32_t depth, uint32_t* rows) {
+  if (!g || !rows || depth < 0 || depth >= g->ix.n_depth) return ESG_EINVAL;
+  esg_index& ix = g->ix;
+  if (hipSetDevice(ix.device) != hipSuccess) return ESG_EHIP;
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(rows, ix.adj + (size_t)depth * ix.n * ix.R, (size_t)ix.n * ix.R * 4,
+                hipMemcpyDeviceToHost) != hipSuccess) {
+    (void)hipGetLastError();
+    return ESG_EHIP;
+  }
+  return ESG_OK;
+}
+
+int32_t gpu_put_rows(GpuState* g, int32_t depth, const uint32_t* rows) {
+  if (!g || !rows || depth < 0 || depth >= g->ix.n_depth) return ESG_EINVAL;
+  esg_index& ix = g->ix;
+  if (hipSetDevice(ix.device) != hipSuccess) return ESG_EHIP;
+  if (hipMemcpy(ix.adj + (size_t)depth * ix.n * ix.R, rows, (size_t)ix.n * ix.R * 4,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    (void)hipGetLastError();
+    return ESG_EHIP;
+  }
+  return ESG_OK;
+}
+
+namespace {
+
+// One chunk of a round (whole jobs, at most max_round points).
+int32_t round_chunk(GpuState* g, int32_t depth, int64_t nb, const uint32_t* pts,
+                    const uint32_t* eps, const uint32_t* lo, const uint32_t* hi,
+                    int32_t max_batch) {
+  esg_index& ix = g->ix;
+  const int R = ix.R, efc = g->efc;
+  // host staging: positions, entries, ranges [lo, hi] of the current graphs
+  g->h64.resize((size_t)nb * 2);
+  for (int64_t i = 0; i < nb; i++) {
+    g->h64[(size_t)i] = lo[i];
+    g->h64[(size_t)(nb + i)] = hi[i];
+  }
+  if (hipDeviceSynchronize() != hipSuccess ||   // the previous round has read these buffers
+      hipMemcpy(g->pts, pts, (size_t)nb * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(g->eps, eps, (size_t)nb * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(g->l, g->h64.data(), (size_t)nb * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(g->r, g->h64.data() + nb, (size_t)nb * 8, hipMemcpyHostToDevice) != hipSuccess)
+    return ESG_EHIP;
+  const unsigned gblocks = (unsigned)std::min<int64_t>(4096, (nb * ix.d + 255) / 256);
+  build_gather_kernel<<<gblocks, 256>>>(ix.vec, ix.dp, ix.d, g->pts, nb, g->qbuf);
+
+  // 1) insertion searches: Alg. 1 from each point's entry on its graph's
+  //    positions, beam width = candidates kept = efc
+  esgk::SearchArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.vec = ix.vec;
+  a.adj = ix.adj;
+  a.ep = g->eps;
+  a.ext_id = ix.ext_id;
+  a.n = ix.n;
+  a.d = ix.d;
+  a.dq = ix.d;
+  a.dp = ix.dp;
+  a.R = R;
+  a.leaf = 1;
+  a.n_depth = ix.n_depth;
+  a.c_den = 2;
+  a.fanout = 2;
+  a.row_base = ix.row_base;
+  a.forced = 1;
+  a.forced_depth = depth;
+  a.queries = g->qbuf;
+  a.l = g->l;
+  a.r = g->r;
+  a.nq = nb;
+  a.k = efc;
+  a.ef = efc;
+  a.cand_cap = efc;
+  a.hop_budget = -1;
+  a.ids = g->cid;
+  a.dists = g->cd;
+  a.spill = ix.spill;
+  a.spill_words = ix.spill_words;
+  a.spill_slots = ix.spill_slots;
+  a.counter = ix.counter;
+  a.hash_cap = g->hash_cap;
+  const void* fn = ix.kt->fn[esgk::kF32][width_index(efc)][0];
+  const size_t slds = (size_t)esgk::kWavesPerGroup * (esgk::kStageBytes + 2 * (size_t)g->hash_cap);
+  int32_t st = launch_search(&ix, a, fn, slds, nb, nullptr);
+  if (st != ESG_OK) return st;
+
+  // 2) forward rows, 3) reverse edges
+  int keycap = 1;
+  while (keycap < std::max(efc, R + max_batch)) keycap <<= 1;
+  esgk::BuildArgs B;
+  std::memset(&B, 0, sizeof(B));
+  B.A = a;
+  B.nb = nb;
+  B.efc = efc;
+  B.R = R;
+  B.keycap = keycap;
+  B.wave_lds = esgk::kStageBytes + keycap * 8 + 32 * 4;
+  B.pts = g->pts;
+  B.cand_ids = g->cid;
+  B.cand_d = g->cd;
+  B.rows = ix.adj + (size_t)depth * ix.n * R;
+  B.cnt = g->cnt;
+  B.start = g->start;
+  B.srcs = g->srcs;
+  B.touched = g->touched;
+  B.counters = g->counters;
+  const int wpb = std::max(1, std::min(esgk::kWavesPerGroup, g->max_lds / B.wave_lds));
+  if (B.wave_lds > g->max_lds) return ESG_EUNSUPPORTED;
+  const size_t blds = (size_t)wpb * B.wave_lds;
+  void* args[] = {&B};
+  if (hipLaunchKernel(ix.kt->build_prune, dim3((unsigned)((nb + wpb - 1) / wpb)), dim3(64 * wpb),
+                      args, blds, nullptr) != hipSuccess)
+    return ESG_EHIP;
+  const int64_t np = nb * R;
+  const unsigned pblocks = (unsigned)((np + 255) / 256);
+  build_reset_kernel<<<1, 1>>>(g->counters);
+  build_count_kernel<<<pblocks, 256>>>(g->pts, nb, B.rows, R, g->cnt, g->touched, g->counters);
+  build_alloc_kernel<<<pblocks, 256>>>(g->touched, g->cnt, g->start, g->fill, g->counters, np);
+  build_fill_kernel<<<pblocks, 256>>>(g->pts, nb, B.rows, R, g->start, g->fill, g->srcs);
+  const unsigned rblocks =
+      (unsigned)std::min<int64_t>((np + wpb - 1) / wpb, (int64_t)ix.cu_count * 16);
+  if (hipLaunchKernel(ix.kt->build_reverse, dim3(rblocks), dim3(64 * wpb), args, blds, nullptr) !=
+      hipSuccess)
+    return ESG_EHIP;
+  return hipGetLastError() == hipSuccess ? ESG_OK : ESG_EHIP;
+}
+
+}  // namespace
+
+int32_t gpu_round(GpuState* g, int32_t depth, int64_t nb, const uint32_t* pts,
+                  const uint32_t* eps, const uint32_t* lo, const uint32_t* hi) {
+  if (!g || depth < 0 || depth >= g->ix.n_depth || nb < 0 || (nb > 0 && (!pts || !eps || !lo || !hi)))
+    return ESG_EINVAL;
+  esg_index& ix = g->ix;
+  for (int64_t i = 0; i < nb; i++)
+    if (pts[i] >= ix.n || eps[i] >= ix.n || lo[i] > hi[i] || hi[i] >= ix.n || pts[i] <= hi[i] ||
+        eps[i] < lo[i] || eps[i] > hi[i])
+      return ESG_EINVAL;
+  if (hipSetDevice(ix.device) != hipSuccess) return ESG_EHIP;
+  // chunks of whole jobs (a job's points are consecutive and share lo)
+  int64_t i0 = 0;
+  while (i0 < nb) {
+    int64_t i1 = i0, max_batch = 0;
+    while (i1 < nb) {
+      int64_t j = i1;
+      while (j < nb && lo[j] == lo[i1]) j++;
+      if (j - i0 > g->max_round && i1 > i0) break;
+      if (j - i1 > g->max_round) return ESG_EINVAL;   // one job's batch exceeds a round
+      max_batch = std::max(max_batch, j - i1);
+      i1 = j;
+    }
+    const int32_t st =
+        round_chunk(g, depth, i1 - i0, pts + i0, eps + i0, lo + i0, hi + i0, (int32_t)max_batch);
+    if (st != ESG_OK) {
+      (void)hipGetLastError();
+      return st;
+    }
+    i0 = i1;
+  }
+  return ESG_OK;
+}
+
+void gpu_close(GpuState* g) {
+  if (!g) return;
+  if (hipSetDevice(g->ix.device) == hipSuccess) (void)hipDeviceSynchronize();
+  g->ix.release();
+  delete g;
+}
+
+}  // namespace esgb

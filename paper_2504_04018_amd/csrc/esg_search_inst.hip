@@ -1,4 +1,5 @@
 // Instantiates the search kernels for one vector dimension (-DESG_DIM=d).
+#include "esg_build_impl.h"
 #include "esg_dispatch.h"
 #include "esg_scan_impl.h"
 
@@ -77,4 +78,7 @@ extern "C" void ESG_CAT(esg_register_dim_, ESG_DIM)(esgk::KernelTable* t) {
   esgk::fill_scan<1>(t, 0);
   esgk::fill_scan<2>(t, 1);
   esgk::fill_scan<4>(t, 2);
+  using S32 = esgk::Shape<esgk::kF32>;
+  t->build_prune = reinterpret_cast<const void*>(&esgk::build_prune_kernel<S32::G, S32::CPL>);
+  t->build_reverse = reinterpret_cast<const void*>(&esgk::build_reverse_kernel<S32::G, S32::CPL>);
 }

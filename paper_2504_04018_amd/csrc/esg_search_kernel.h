@@ -369,7 +369,13 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
   const int64_t lq = A.l[qi], rq = A.r[qi];
   const bool valid = lq >= 0 && rq < A.n && lq <= rq;
   Part pt{};
-  const int np = valid ? select_parts(A, lq, rq, 0, pt) : 0;
+  int np = 0;
+  if (valid && A.forced) {
+    pt = Part{1, A.forced_depth, qi, (uint32_t)lq, (uint32_t)rq, (uint32_t)lq, (uint32_t)rq};
+    np = 1;
+  } else if (valid) {
+    np = select_parts(A, lq, rq, 0, pt);
+  }
   if (!valid || np < 0) {
     for (int i = lane; i < k; i += kWave) {
       ids[i] = -1;
