@@ -155,7 +155,7 @@ int32_t esg_build_index(const float* vecs, const double* attr, int64_t n, int32_
  * summation order of the search kernels on both paths.  Entry points
  * (medoids in float64) and the reachability repair stay on the host
  * between depths.  Writes the same file as esg_build_index for the same
- * inputs and parameters.  Needs batch_max <= 65536 and a dimension with
+ * inputs and parameters.  Needs batch_max <= 8192 and a dimension with
  * compiled kernels.  Device memory: the vectors (4 n d bytes), every
  * depth's rows (4 n R n_depth), the search workspace of a loaded index,
  * and buffers for rounds of up to 65,536 points.

@@ -552,8 +552,10 @@ struct GpuHolder {
   }
 };
 
-// Points of one device insertion round at most (a job's batch must fit).
+// Points of one device insertion round at most, and the largest batch of
+// one node on the device (its reverse-edge groups are sorted in LDS).
 constexpr int64_t kGpuRound = 65536;
+constexpr int32_t kGpuBatchMax = 8192;
 
 int32_t build_chains(const float* X, const std::vector<int64_t>& order,
                      const std::vector<double>& sorted_attr, int64_t n, int32_t d,
@@ -624,7 +626,7 @@ static int32_t build_impl(const float* vecs, const double* attr, int64_t n, int3
     return ESG_EINVAL;
   const int fanout = P.fanout == 0 ? 2 : P.fanout;
   if (fanout > ESG_FANOUT_MAX) return ESG_EUNSUPPORTED;
-  if (device >= 0 && P.batch_max > kGpuRound) return ESG_EINVAL;
+  if (device >= 0 && P.batch_max > kGpuBatchMax) return ESG_EINVAL;
   for (int64_t i = 0; i < n; i++)
     if (std::isnan(attr[i])) return ESG_EINVAL;
   try {

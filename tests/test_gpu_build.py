@@ -61,7 +61,7 @@ def test_gpu_build_equals_host_build(case, tmp_path):
 def test_gpu_build_rejects_bad_arguments(tmp_path):
     X = np.ones((100, 32), np.float32)
     with pytest.raises(esg.EsgError) as e:
-        esg.build_index(X, np.arange(100.0), str(tmp_path / "x"), device=0, batch_max=1 << 17)
+        esg.build_index(X, np.arange(100.0), str(tmp_path / "x"), device=0, batch_max=8193)
     assert e.value.status == esg.ESG_EINVAL
     with pytest.raises(esg.EsgError) as e:
         esg.build_index(np.ones((100, 8), np.float32), np.arange(100.0), str(tmp_path / "y"),
