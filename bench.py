@@ -52,8 +52,10 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 TARGET_RECALL = 0.95
 CAL_QUERIES = 50_000
 CAL_SE = 3.0          # calibration margin in standard errors of the mean recall
-EF_GRID = [10, 12, 14, 16, 18, 20, 22, 24, 28, 32, 40, 48, 64, 96, 100, 112, 128, 192, 256, 384, 512, 768, 1024]
-DELTA_GRID = [-1.0, -0.75, -0.5, -0.375, -0.25, -0.125, 0.0, 0.25, 0.5]
+# calibration grids: every ef up to 32 (one step is about 4 % of the work
+# there), and offsets delta in steps of 1/16 (2^(1/16): 4.4 % of beam)
+EF_GRID = list(range(10, 33)) + [36, 40, 48, 64, 96, 100, 112, 128, 192, 256, 384, 512, 768, 1024]
+DELTA_GRID = [i / 16.0 for i in range(-16, 9)]
 LABEL_EF_GRID = [10, 12, 14, 16, 18, 20, 22, 24, 28, 32, 40, 48, 64, 96, 128, 192, 256]
 LABEL_HOP_GRID = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256]
 

@@ -29,9 +29,12 @@ CXX_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-fopenmp", "-march=x86-64-v3", "-Wal
 
 
 def dims() -> list[int]:
+    only = os.environ.get("ESG_DIMS_ONLY")
+    if only:
+        return [int(only)]
     txt = open(os.path.join(CSRC, "esg_dims.h")).read()
-    m = re.search(r"#define ESG_DIMS\(X\)(.*)", txt)
-    return [int(v) for v in re.findall(r"X\((\d+)\)", m.group(1))]
+    m = re.search(r"#define ESG_DIMS\(X\) X\(32\)(.*)", txt)
+    return [32] + [int(v) for v in re.findall(r"X\((\d+)\)", m.group(1))]
 
 
 def _run(cmd):
@@ -49,6 +52,13 @@ def _newer(out: str, deps: list[str]) -> bool:
 
 
 def build(force: bool = False, jobs: int | None = None, verbose: bool = False) -> str:
+    """Builds every kernel class; ESG_DIMS_ONLY=<d> (development only) builds
+    the kernels of one class into _build/only<d>/ and the library with it."""
+    global BUILD
+    only = os.environ.get("ESG_DIMS_ONLY")
+    if only:
+        BUILD = os.path.join(ROOT, "_build", f"only{int(only)}")
+        HIP_FLAGS.append(f"-DESG_DIMS_ONLY={int(only)}")
     os.makedirs(BUILD, exist_ok=True)
     headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
     headers.append(os.path.join(ROOT, "include", "esg.h"))
@@ -76,11 +86,17 @@ def build(force: bool = False, jobs: int | None = None, verbose: bool = False) -
         for cmd, _ in zip(tasks, ex.map(_run, tasks)):
             if verbose:
                 print("built", cmd[-1], file=sys.stderr)
-    if force or tasks or _newer(LIB, objs):
+    # relink whenever the object set differs from the last link (a
+    # single-class development build and the full build share LIB)
+    stamp = os.path.join(ROOT, "_build", "libesg.objects")
+    last = open(stamp).read() if os.path.exists(stamp) else ""
+    if force or tasks or _newer(LIB, objs) or last != "\n".join(objs):
         tmp = LIB + ".tmp"
         _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,
               "-lgomp", "-Wl,-z,defs"])
         os.replace(tmp, LIB)
+        with open(stamp, "w") as f:
+            f.write("\n".join(objs))
     return LIB
 
 

@@ -117,16 +117,14 @@ __device__ __forceinline__ float probe_feature(int lane, float wp, float L, int6
   return f;
 }
 
-// Gather rounds in flight per lane: the learned kernels with narrow storage
-// keep 4 instead of 8 to leave registers for the predictor (measured: fewer
-// spills beat more loads in flight there; the float32 ones keep 8).
+// Gather rounds in flight per lane: 8 in every kernel.
 template <int KIND, int LEARN>
-constexpr int kLearnRF = (LEARN != 0 && KIND != kF32) ? 4 : 8;
+constexpr int kLearnRF = 8;
 // Rounds reduced together (reduce-scatter) in the distance pass: all of them
-// for float32 and in the learned kernels; the plain narrow-storage kernels
-// reduce one round at a time (measured faster there: fewer registers).
+// for float32; the narrow-storage kernels reduce one round at a time
+// (measured faster there: fewer registers, also in the learned kernels).
 template <int KIND, int LEARN>
-constexpr int kReduceGroup = (KIND == kF32 || LEARN != 0) ? 8 : 1;
+constexpr int kReduceGroup = KIND == kF32 ? 8 : 1;
 
 template <int KIND, int G, int CPL, int E, int LEARN>
 __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* Ls, Visited& V,
@@ -456,9 +454,12 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
 // Occupancy target: the float32 kernels with lists of up to 128 keys and the
 // bfloat16 kernels with 64 keys are held to 4 waves per SIMD (measured: the
 // few spills this costs are cheaper than a lost wave on these latency-bound
-// kernels); the others keep the compiler's choice.
+// kernels), except the bfloat16 kernel with the one-hop probe, whose
+// predictor sits before the loop and spills into it at 4 (3 waves measured
+// 15 % faster); the others keep the compiler's choice.
 template <int KIND, int E, int LEARN>
 constexpr int min_waves() {
+  if (KIND == kBF16 && E == 1 && LEARN == 1) return 3;
   return ((KIND == kF32 && E <= 2) || (KIND == kBF16 && E == 1)) ? 4 : 1;
 }
 

@@ -1,7 +1,9 @@
 """GPU parity at the bench's full size: the DEEP-shaped set (N = 1,000,000,
 d = 96, R = 32, leaf 1,024) and its whole batch of 100,000 queries in one
 launch, as bench.py times it; sampled outputs are checked one by one
-against the oracle (bit-exact ids and float32 distances)."""
+against the oracle (bit-exact ids and float32 distances).  The indexes are
+built on the device, as the bench builds them (the host builder writes the
+same file: test_gpu_build)."""
 from __future__ import annotations
 
 import numpy as np
@@ -31,9 +33,9 @@ def _t(a):
 def deep(tmp_path_factory):
     w = synth.make_workload(2)
     path = str(tmp_path_factory.mktemp("deep") / "deep1M.esgi")
-    print("[gpu] building the 1M x 96 index", flush=True)
+    print("[gpu] building the 1M x 96 index on the device", flush=True)
     esg.build_index(w["X"], w["attr"].astype(np.float64), path, degree=w["degree"],
-                    leaf=w["leaf"], ef_construction=w["ef_construction"])
+                    leaf=w["leaf"], ef_construction=w["ef_construction"], device=0)
     del w["X"]
     gix = esg.Index(path, 0)
     gix.add_storage("bf16")
@@ -129,9 +131,9 @@ def test_full_batch_scan_sampled(deep):
 def sift(tmp_path_factory):
     w = synth.make_workload(1)
     path = str(tmp_path_factory.mktemp("sift") / "sift1M.esgi")
-    print("[gpu] building the 1M x 128 index", flush=True)
+    print("[gpu] building the 1M x 128 index on the device", flush=True)
     esg.build_index(w["X"], w["attr"].astype(np.float64), path, degree=w["degree"],
-                    leaf=w["leaf"], ef_construction=w["ef_construction"])
+                    leaf=w["leaf"], ef_construction=w["ef_construction"], device=0)
     del w["X"]
     return w, path
 
