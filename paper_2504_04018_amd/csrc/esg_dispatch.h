@@ -15,6 +15,7 @@ struct KernelTable {
   const void* rerank[kNumScanWidths];     // merge + float32 rerank + certificate
   const void* fallback[kNumScanWidths];   // exact float32 scan of each window
   const void* fb_merge[kNumScanWidths];   // merge of the windows' exact lists
+  const void* build_search[kNumWidths];   // builder: float32 insertion searches
   const void* build_prune;                // builder: forward rows by occlusion
   const void* build_reverse;              // builder: reverse edges
 };

@@ -12,6 +12,10 @@ constexpr int kBatch = 32;          // adjacency slots handled per expansion (ma
 constexpr int kStageBytes = 1024;   // per-wave LDS staging ahead of the hash
 
 enum DistKind : int { kF32 = 0, kBF16 = 1, kFP8 = 2 };
+// Search kernel variants (template argument LEARN): 0 plain, 1 learned
+// switch after a one-hop probe, 2 after a longer probe, kBuildSearch the
+// builder's insertion search (plain, with the part given per query).
+constexpr int kBuildSearch = 3;
 
 // Beam-width predictor: 12 features -> 64 -> 64 -> 1 (ReLU), float32.
 // Parameter layout: W1[64][12] b1[64] W2[64][64] b2[64] W3[64] b3[1]
@@ -45,9 +49,9 @@ struct SearchArgs {
   int32_t fanout;         // children per tree node (the chains' base in layout 1)
   int32_t layout;         // 0: segment tree; 1: prefix and suffix chains (half-bounded index)
   const int64_t* row_base;// [n_depth]: row of position p at depth t is adj + (row_base[t] + p) R
-  // builder's insertion searches: when `forced` is set, query i searches
-  // the graph at depth forced_depth on [l[i], r[i]] from ep[i] (no Alg. 4)
-  int32_t forced, forced_depth;
+  // builder's insertion searches (the kBuildSearch kernels): query i
+  // searches the graph of depth forced_depth on [l[i], r[i]] from ep[i]
+  int32_t forced_depth;
   // batch
   const float* queries;   // [nq][dq]
   const int64_t* l;

@@ -1175,7 +1175,7 @@ int32_t gpu_open(int32_t device, const float* X, int64_t n, int32_t d, int32_t R
   const esgk::KernelTable* kt = nullptr;
   for (const auto& t : kernel_tables())
     if (!kt && same_shape(d, t.dim)) kt = &t;
-  if (!kt || !kt->build_prune || !kt->fn[esgk::kF32][width_index(efc)][0]) return ESG_EUNSUPPORTED;
+  if (!kt || !kt->build_prune || !kt->build_search[width_index(efc)]) return ESG_EUNSUPPORTED;
   // the visited hash keeps the low bits of a node-local key: <= 12 spare bits
   int kb = 0;
   while (kb < 32 && ((int64_t)1 << kb) < n) kb++;
@@ -1358,7 +1358,6 @@ int32_t round_chunk(GpuState* g, int32_t depth, int64_t nb, const uint32_t* pts,
   a.c_den = 2;
   a.fanout = 2;
   a.row_base = ix.row_base;
-  a.forced = 1;
   a.forced_depth = depth;
   a.queries = g->qbuf;
   a.l = g->l;
@@ -1375,7 +1374,7 @@ int32_t round_chunk(GpuState* g, int32_t depth, int64_t nb, const uint32_t* pts,
   a.spill_slots = ix.spill_slots;
   a.counter = ix.counter;
   a.hash_cap = g->hash_cap;
-  const void* fn = ix.kt->fn[esgk::kF32][width_index(efc)][0];
+  const void* fn = ix.kt->build_search[width_index(efc)];
   const size_t slds = (size_t)esgk::kWavesPerGroup * (esgk::kStageBytes + 2 * (size_t)g->hash_cap);
   int32_t st = launch_search(&ix, a, fn, slds, nb, nullptr);
   if (st != ESG_OK) return st;

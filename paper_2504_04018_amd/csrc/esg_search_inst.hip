@@ -78,6 +78,11 @@ extern "C" void ESG_CAT(esg_register_dim_, ESG_DIM)(esgk::KernelTable* t) {
   esgk::fill_scan<1>(t, 0);
   esgk::fill_scan<2>(t, 1);
   esgk::fill_scan<4>(t, 2);
+  t->build_search[0] = esgk::kernel_ptr<esgk::kF32, 1, esgk::kBuildSearch>();
+  t->build_search[1] = esgk::kernel_ptr<esgk::kF32, 2, esgk::kBuildSearch>();
+  t->build_search[2] = esgk::kernel_ptr<esgk::kF32, 4, esgk::kBuildSearch>();
+  t->build_search[3] = esgk::kernel_ptr<esgk::kF32, 8, esgk::kBuildSearch>();
+  t->build_search[4] = esgk::kernel_ptr<esgk::kF32, 16, esgk::kBuildSearch>();
   using S32 = esgk::Shape<esgk::kF32>;
   t->build_prune = reinterpret_cast<const void*>(&esgk::build_prune_kernel<S32::G, S32::CPL>);
   t->build_reverse = reinterpret_cast<const void*>(&esgk::build_reverse_kernel<S32::G, S32::CPL>);

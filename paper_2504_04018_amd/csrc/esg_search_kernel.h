@@ -251,8 +251,9 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
   // next candidate passes the stop test); P's fill counts its live part
   // (candidates not farther than a full Q's worst), which the lossless
   // prune leaves unchanged.
-  const uint64_t worst0 = (LEARN != 0 && go) ? list_at(Q, m - 1) : kKeyInf;
-  if (LEARN != 0 && go && u != kKeyInf && hops == A.probe_hops && !(worst0 < u)) {
+  constexpr bool kLearned = LEARN == 1 || LEARN == 2;
+  const uint64_t worst0 = (kLearned && go) ? list_at(Q, m - 1) : kKeyInf;
+  if (kLearned && go && u != kKeyInf && hops == A.probe_hops && !(worst0 < u)) {
     // probe over: features -> predicted beam width or stopping step
     int qsize = 0, psize = 0;
 #pragma unroll
@@ -368,11 +369,12 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
   const bool valid = lq >= 0 && rq < A.n && lq <= rq;
   Part pt{};
   int np = 0;
-  if (valid && A.forced) {
-    pt = Part{1, A.forced_depth, qi, (uint32_t)lq, (uint32_t)rq, (uint32_t)lq, (uint32_t)rq};
-    np = 1;
-  } else if (valid) {
-    np = select_parts(A, lq, rq, 0, pt);
+  if constexpr (LEARN == kBuildSearch) {
+    // the builder's insertion search: the graph of one depth on [l, r]
+    if (valid) pt = Part{1, A.forced_depth, qi, (uint32_t)lq, (uint32_t)rq, (uint32_t)lq, (uint32_t)rq};
+    np = valid ? 1 : 0;
+  } else {
+    np = valid ? select_parts(A, lq, rq, 0, pt) : 0;
   }
   if (!valid || np < 0) {
     for (int i = lane; i < k; i += kWave) {
