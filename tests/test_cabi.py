@@ -338,3 +338,27 @@ def test_metric_builder_errors(tmp_path):
     st = esg.lib().esg_build_index(X.ctypes.data, np.arange(10.0).ctypes.data, 10, 4,
                                    ctypes.byref(p), str(tmp_path / "y").encode())
     assert st == esg.ESG_EINVAL
+
+
+def test_gpu_builder_argument_checks(tmp_path):
+    """The device builder's host-side checks, which run before any device
+    call: a negative device and a node batch above 8,192 are refused; here
+    (no HIP device) a valid call reports the missing device."""
+    X = np.ones((50, 32), np.float32)
+    p = esg.BuildParams(16, 8, 16, 2, 1, 0, 0, 0, 0)
+    out = str(tmp_path / "g").encode()
+    L = esg.lib()
+    assert L.esg_build_index_gpu(X.ctypes.data, np.arange(50.0).ctypes.data, 50, 32,
+                                 ctypes.byref(p), -1, out) == esg.ESG_EINVAL
+    p.batch_max = 8193
+    assert L.esg_build_index_gpu(X.ctypes.data, np.arange(50.0).ctypes.data, 50, 32,
+                                 ctypes.byref(p), 0, out) == esg.ESG_EINVAL
+    p.batch_max = 0
+    st = L.esg_build_index_gpu(X.ctypes.data, np.arange(50.0).ctypes.data, 50, 32,
+                               ctypes.byref(p), 0, out)
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except ImportError:
+        has_gpu = False
+    assert st == (esg.ESG_OK if has_gpu else esg.ESG_EHIP)
