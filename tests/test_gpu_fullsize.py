@@ -1,6 +1,7 @@
 """GPU parity at the bench's full size: the DEEP-shaped set (N = 1,000,000,
 d = 96, R = 32, leaf 1,024) and its whole batch of 100,000 queries in one
-launch, as bench.py times it; sampled outputs are checked one by one
+launch, as bench.py times it, the SIFT-shaped set (1M x 128) and the
+embedding-shaped set (2M x 768, k = 100); sampled outputs are checked one by one
 against the oracle (bit-exact ids and float32 distances).  The indexes are
 built on the device, as the bench builds them (the host builder writes the
 same file: test_gpu_build)."""
@@ -165,3 +166,47 @@ def test_sift_full_size_sampled_parity(sift, trav):
     assert np.all(st == 0)
     assert np.array_equal(ids[s], oid)
     assert np.array_equal(dists[s].view(np.uint32), od.view(np.uint32))
+
+
+@pytest.fixture(scope="module")
+def embedding(tmp_path_factory):
+    """The embedding-shaped set at full size (N = 2,000,000, d = 768, R = 32,
+    leaf 1,024; 20,000 queries in 13 width buckets, k = 100)."""
+    w = synth.make_workload(3)
+    path = str(tmp_path_factory.mktemp("emb") / "emb2M.esgi")
+    print("[gpu] building the 2M x 768 index on the device", flush=True)
+    esg.build_index(w["X"], w["attr"].astype(np.float64), path, degree=w["degree"],
+                    leaf=w["leaf"], ef_construction=w["ef_construction"], device=0)
+    del w["X"]
+    gix = esg.Index(path, 0)
+    yield w, gix, path
+    gix.free()
+
+
+def test_embedding_full_size_sampled_parity(embedding):
+    """The 20,000-query batch in one launch (float32 traversal, k = 100, ef
+    112, the bench's calibrated beam): 16 sampled queries bit-exact against
+    the oracle; and the exact scan (k = 100) on 8 sampled queries equal to
+    the oracle's float32 scan."""
+    w, gix, path = embedding
+    Q, l, r = w["Q"], w["l"], w["r"]
+    nq, k = len(Q), w["k"]
+    print(f"[gpu] embedding full batch {nq} queries k={k} ef=112", flush=True)
+    ids, dists = gix.search_ex(_t(Q), _t(l), _t(r), k, 112)
+    torch.cuda.synchronize()
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    oix = oracle.read_index(path)
+    s = np.sort(np.random.default_rng(11).choice(nq, 16, replace=False))
+    oid, od, st = oracle.query_batch(oix, Q[s], l[s], r[s], k, 112)
+    assert np.all(st == 0)
+    assert np.array_equal(ids[s], oid)
+    assert np.array_equal(dists[s].view(np.uint32), od.view(np.uint32))
+    gix.add_storage("bf16")
+    gix.reserve(nq, 4_500_000)
+    print("[gpu] embedding exact scan", flush=True)
+    sids, sd, nfb = gix.scan(_t(Q), _t(l), _t(r), k)
+    torch.cuda.synchronize()
+    s = np.sort(np.random.default_rng(12).choice(nq, 8, replace=False))
+    oid, od = oracle_scan(oix, Q[s], l[s], r[s], k)
+    assert np.array_equal(sids.cpu().numpy()[s], oid)
+    assert np.array_equal(sd.cpu().numpy()[s].view(np.uint32), od.view(np.uint32))
