@@ -75,8 +75,9 @@ def parse():
     ap.add_argument("--nq", type=int, default=None, help="shrink the query count")
     ap.add_argument("--ntrain", type=int, default=200_000, help="training traces")
     ap.add_argument("--ef-max", type=int, default=32, help="beam of the learned form")
-    ap.add_argument("--probe-hops", type=int, nargs="+", default=[1, 4],
-                    help="probe lengths of the learned form (one network each)")
+    ap.add_argument("--probe-hops", type=int, nargs="+", default=[0, 1, 4],
+                    help="probe lengths of the learned form (one network each; 0: beams "
+                         "chosen before the search from the selection features)")
     ap.add_argument("--reps", type=int, default=5, help="timed repetitions per sweep point")
     ap.add_argument("--cache-dir", default=os.environ.get("ESG_BENCH_CACHE", "/tmp/esg_bench"))
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -654,8 +655,8 @@ def main():
         nets = []
         for probe in args.probe_hops:
             for target, grid in (("ef", LABEL_EF_GRID), ("hops", LABEL_HOP_GRID)):
-                if args.target and target != args.target:
-                    continue
+                if (args.target and target != args.target) or (probe == 0 and target == "hops"):
+                    continue                 # a stopping step needs a probe
                 t1 = time.time()
                 g = [v for v in grid if target == "hops" or v <= args.ef_max]
                 F, T = learned.traces(ix, Qt, lt, rt, k, g, args.ef_max, probe, tkw, gt_dt,

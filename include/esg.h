@@ -269,9 +269,18 @@ typedef struct {
                             esg_mlp_forward; each call copies the weights
                             into the index's own inference layout on the
                             call's stream first (read-only here)          */
-  int32_t probe_hops;    /* > 0 with mlp (or with feat_out alone: features
-                            only, no change of beam).  1 selects a kernel
-                            whose switch comes before its search loop     */
+  int32_t probe_hops;    /* with mlp (or with feat_out alone: features
+                            only, no change of beam): > 0 as above (1
+                            selects a kernel whose switch comes before its
+                            search loop); 0: the beam of every graph part
+                            is chosen before the search from its selection
+                            features alone (log2 of its filter width and
+                            node size, their ratio, log2 of the query
+                            width, parts - 1; the seven probe-state
+                            features are 0), then the plain kernel runs
+                            each part with m = cand_cap = ef'; needs a
+                            reservation of >= nq queries and
+                            mlp_target = 0                                */
   float mlp_delta;       /* calibration offset added to y                   */
   int32_t mlp_target;    /* 0: y sets the beam width as above; 1: y sets the
                             stopping step instead -- the part may take at
@@ -280,8 +289,8 @@ typedef struct {
   float* feat_out;       /* device float [nq][2][16] or NULL: per graph part
                             the 12 features, y and ef' (or the granted
                             expansions when mlp_target = 1) (parts that end
-                            before or right at the end of the probe are
-                            left untouched)                               */
+                            before or right at the end of the probe, and
+                            leaf scans, are left untouched)               */
   esg_part_trace* trace; /* device [nq][2] or NULL                          */
   uint32_t* visited;     /* device [nq][2][visited_cap] or NULL: visited positions */
   int64_t visited_cap;   /* capacity per part of `visited`                  */
@@ -295,8 +304,8 @@ typedef struct {
  * 64 reserved per window (E = 1, 2, 4 for k <= 32, 64, 128), so a call
  * handles max_windows / E windows at once: esg_scan_batch splits larger
  * batches into several passes, the router returns ERANGE.  Also holds the
- * one-hop learned form's per-part buffers.  Allocates; call it once before
- * searching.  Errors: EINVAL, ENOMEM. */
+ * per-part beams of the learned form without a probe (probe_hops = 0).
+ * Allocates; call it once before searching.  Errors: EINVAL, ENOMEM. */
 int32_t esg_index_reserve(esg_index* idx, int64_t max_queries, int64_t max_windows);
 
 typedef struct {

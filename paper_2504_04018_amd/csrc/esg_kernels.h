@@ -77,6 +77,7 @@ struct SearchArgs {
   const float* mlp;       // packed parameters (kMlpParams floats: W1, W2 input-major) or null
   float* feat_out;        // [nq][2][kFeatStride] features, raw output and ef' (optional)
   int32_t probe_hops;
+  const int32_t* part_ef; // [nq][2] beam of each graph part chosen before the search, or null
   float mlp_delta;        // calibration offset added to the predicted log2 value
   int32_t mlp_target;     // 0: the output sets the beam width, 1: the remaining hops
   const int32_t* qlist;   // queries to process (null = 0..nq-1)

@@ -92,6 +92,7 @@ struct esg_index {
   int32_t* wide = nullptr;
   int32_t* counts = nullptr;    // [0] narrow, [1] wide, [2] fallback, [3..] bucket histogram
   int32_t* fb_list = nullptr;
+  int32_t* part_ef = nullptr;   // [res_queries][2] beams chosen before the search
   uint64_t* cand = nullptr;      // [res_windows * 64] per-window candidate lists
   int nbuckets = 0, bucket_shift = 11;
   hipStream_t capture_stream = nullptr;
@@ -146,6 +147,52 @@ __global__ void mlp_pack_kernel(const float* __restrict__ src, float* __restrict
     from = kOffW2 + h * kHidden + 4 * c + e;
   }
   dst[j] = src[from];
+}
+
+// Learned beam width chosen before the search (probe_hops = 0): one wave
+// per query runs Alg. 4, and for each graph part the network maps the
+// part's selection features (log2 of its filter width and node size, their
+// ratio, log2 of the query width, parts - 1; the probe-state features are
+// 0) to y; the part's beam is ef' = clamp(ceil(2^(y + delta)), k, ef).
+// Writes the features, y and ef' to feat_out when given; with no network
+// only the features.
+__global__ __launch_bounds__(256) void predict_beams_kernel(esgk::SearchArgs A, int32_t* part_ef) {
+  using namespace esgk;
+  __shared__ WaveLds stage[kWavesPerGroup];
+  const int lane = lane_id();
+  const int wave = (int)(threadIdx.x >> 6);
+  const int64_t qi = (int64_t)blockIdx.x * kWavesPerGroup + wave;
+  if (qi >= A.nq) return;
+  const int64_t lq = A.l[qi], rq = A.r[qi];
+  int np = 0;
+  Part pt{};
+  if (lq >= 0 && rq < A.n && lq <= rq) np = select_parts(A, lq, rq, 0, pt);
+  for (int p = 0; p < 2; p++) {
+    if (p == 1 && np == 2) select_parts(A, lq, rq, 1, pt);
+    int efp = A.ef;
+    if (p < np && pt.kind == 1) {
+      const float f = lane < 5 ? probe_feature(lane, (float)(pt.y - pt.x + 1),
+                                               (float)(pt.b - pt.a + 1), rq - lq + 1, np, 0, 1,
+                                               0, A.k, 0, 0, 0.0f, 0.0f, 0.0f, 1.0f)
+                               : 0.0f;
+      float y = 0.0f;
+      if (A.mlp) {
+        y = mlp_infer(A.mlp, f, &stage[wave], lane);
+        const float e2 = exp2f(y + A.mlp_delta);
+        efp = e2 >= (float)A.ef ? A.ef : (int)ceilf(e2);
+        efp = efp < A.k ? A.k : efp;
+      }
+      if (A.feat_out) {
+        float* out = A.feat_out + (qi * 2 + p) * kFeatStride;
+        if (lane < kFeat) out[lane] = f;
+        if (lane == 0) {
+          out[kFeat] = y;
+          out[kFeat + 1] = (float)efp;
+        }
+      }
+    }
+    if (lane == 0 && part_ef) part_ef[qi * 2 + p] = efp;
+  }
 }
 
 // float32 -> bfloat16, round to nearest even (finite inputs).
@@ -658,6 +705,7 @@ int32_t esg_index_reserve(esg_index* idx, int64_t max_queries, int64_t max_windo
   A((void**)&idx->qlist, Q * 4);
   A((void**)&idx->wide, Q * 4);
   A((void**)&idx->fb_list, Q * 4);
+  A((void**)&idx->part_ef, Q * 8);
   A((void**)&idx->counts, (size_t)(4 + idx->nbuckets) * 4);
   A((void**)&idx->cand, W * 64 * 8);
   if (st != ESG_OK) return st;
@@ -953,6 +1001,9 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   }
 
   // kernel: plain, or with the learned switch after a one-hop or a longer probe
+  // probe_hops = 0 with a network (or feat_out): beams chosen before the
+  // search by predict_beams_kernel, then the plain kernel
+  const bool predict = (o.mlp || o.feat_out) && o.probe_hops == 0;
   const int learn = ((o.mlp || o.feat_out) && o.probe_hops > 0) ? (o.probe_hops == 1 ? 1 : 2) : 0;
   const void* fn = idx->kt->fn[o.traversal][width_index(std::max(ef, cand_cap))][learn];
   if (!fn) return ESG_EUNSUPPORTED;
@@ -997,13 +1048,24 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   a.spill_slots = idx->spill_slots;
   a.counter = idx->counter;
   a.hash_cap = hash_cap;
-  if (o.probe_hops < 0 || (o.mlp && o.probe_hops < 1)) return ESG_EINVAL;
+  if (o.probe_hops < 0) return ESG_EINVAL;
   a.mlp = o.mlp ? idx->mlp_pack : nullptr;
   a.feat_out = o.feat_out;
   a.probe_hops = (o.mlp || o.feat_out) ? o.probe_hops : 0;
   a.mlp_delta = o.mlp_delta;
   if (o.mlp_target < 0 || o.mlp_target > 1) return ESG_EINVAL;
   a.mlp_target = o.mlp_target;
+  esgk::SearchArgs pa = a;   // the predictor's arguments
+  if (predict) {
+    if (o.mlp_target != 0) return ESG_EINVAL;   // a stopping step needs a probe
+    if (nq > idx->res_queries) return ESG_ERANGE;
+    pa.mlp = a.mlp;
+    pa.feat_out = o.feat_out;
+    a.mlp = nullptr;
+    a.feat_out = nullptr;
+    a.probe_hops = 0;
+    if (o.mlp) a.part_ef = idx->part_ef;
+  }
 
   if (hipSetDevice(idx->device) != hipSuccess) return ESG_EHIP;
   const size_t lds = (size_t)esgk::kWavesPerGroup * (esgk::kStageBytes + 2 * (size_t)hash_cap);
@@ -1011,6 +1073,11 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   auto sequence = [&](hipStream_t st) -> int32_t {
     if (o.mlp) {
       mlp_pack_kernel<<<(esgk::kMlpParams + 255) / 256, 256, 0, st>>>(o.mlp, idx->mlp_pack);
+      if (hipGetLastError() != hipSuccess) return ESG_EHIP;
+    }
+    if (predict && nq > 0) {
+      predict_beams_kernel<<<(unsigned)((nq + esgk::kWavesPerGroup - 1) / esgk::kWavesPerGroup),
+                             64 * esgk::kWavesPerGroup, 0, st>>>(pa, idx->part_ef);
       if (hipGetLastError() != hipSuccess) return ESG_EHIP;
     }
     return o.router_threshold > 0 ? launch_routed(idx, a, fn, lds, o.router_threshold, mr, st)

@@ -415,7 +415,10 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
       pc.w_query = rq - lq + 1;
       pc.n_parts = np;
       pc.feat = A.feat_out ? A.feat_out + (qi * 2 + p) * kFeatStride : nullptr;
-      st = search_graph<KIND, G, CPL, E, LEARN>(A, Ls, V, pt, m, cap_p, qr, Qp, dump, lane, pc);
+      // a beam chosen per part before the search (m = cand_cap = ef')
+      const int mp = A.part_ef ? A.part_ef[qi * 2 + p] : m;
+      const int cp = A.part_ef ? mp : cap_p;
+      st = search_graph<KIND, G, CPL, E, LEARN>(A, Ls, V, pt, mp, cp, qr, Qp, dump, lane, pc);
       if constexpr (KIND != kF32)
         if (A.rerank) {
           float qr32[CPL32][4];

@@ -168,6 +168,56 @@ def test_learned_search_parity(tiny, delta, probe):
     assert switched > 50
 
 
+@pytest.mark.parametrize("delta", [0.0, 1.5, -1.0])
+def test_learned_before_search_parity(tiny, delta):
+    """Beams chosen before the search (probe_hops = 0): each graph part's
+    selection features equal the oracle's (1e-4), the other seven are 0,
+    y equals the float64 forward of those features (1e-3), and the plain
+    search with the chosen per-part beams equals the oracle's switch at hop
+    0 (a search with that beam from the start), ids and distances bit for
+    bit."""
+    w, gix, oix = tiny
+    rng = np.random.default_rng(5)
+    p = random_params(rng, 0.15)
+    p[5057:5069] = [10, 10, 0.5, 11, 0.5, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0]
+    p[5069:] = [3, 3, 0.3, 3, 0.5, 1e-3, 1e-3, 1e-3, 1e-3, 1e-3, 1e-3, 1e-3]
+    p[5056] = 5.0
+    nq = len(w["Q"])
+    Q, l, r = w["Q"], w["l"], w["r"]
+    gix.reserve(max(nq, 4096), 65536)
+    feat = torch.full((nq, 2, 16), float("nan"), device=DEV)
+    ef_max, k = 128, 10
+    print(f"[gpu] learned beams before the search, delta {delta}", flush=True)
+    ids, dists = gix.search_ex(_t(Q), _t(l), _t(r), k, ef_max, mlp=_t(p), probe_hops=0,
+                               mlp_delta=delta, feat_out=feat)
+    torch.cuda.synchronize()
+    F = feat.cpu().numpy()
+    ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+    chosen = []
+    for i in range(nq):
+        parts, npart = oracle.select(oix.n, oix.leaf, int(l[i]), int(r[i]))
+        ef2 = np.zeros(2, np.int32)
+        for j, pt in enumerate(parts):
+            if pt["kind"] != oracle.KIND_GRAPH:
+                assert np.isnan(F[i, j, 0])
+                continue
+            _, _, _, _, _, f64 = oracle.search_part_learned(
+                oix, pt, Q[i], ef_max, 0, 0, k, int(r[i] - l[i] + 1), npart)
+            got = F[i, j]
+            assert np.allclose(got[:5], f64[:5], rtol=1e-4, atol=1e-5), (i, j, got[:5], f64[:5])
+            assert np.all(got[5:12] == 0.0)
+            y64, _ = oracle.mlp_forward64(p.astype(np.float64), got[None, :12].astype(np.float32))
+            assert abs(got[12] - y64[0]) <= 1e-3 * (1 + abs(y64[0]))
+            ef2[j] = int(got[13])
+            assert k <= ef2[j] <= ef_max
+            chosen.append(ef2[j])
+        oid, od, _, st = oracle.query_learned(oix, Q[i], int(l[i]), int(r[i]), k, ef_max, 0, ef2)
+        assert st == 0
+        assert np.array_equal(ids[i], oid), i
+        assert np.array_equal(dists[i].view(np.uint32), od.view(np.uint32)), i
+    assert len(chosen) > 100 and len(set(chosen)) > 3    # the beams do vary per part
+
+
 @pytest.mark.parametrize("delta,probe", [(0.0, 4), (2.0, 8), (1.0, 1)])
 def test_learned_stop_parity(tiny, delta, probe):
     """Stopping-step target: every switched part takes at most the granted
