@@ -156,12 +156,25 @@ __global__ void mlp_pack_kernel(const float* __restrict__ src, float* __restrict
 // 0) to y; the part's beam is ef' = clamp(ceil(2^(y + delta)), k, ef).
 // Writes the features, y and ef' to feat_out when given; with no network
 // only the features.
-__global__ __launch_bounds__(256) void predict_beams_kernel(esgk::SearchArgs A, int32_t* part_ef) {
+// Learned beam width chosen before the search (probe_hops = 0), one
+// thread per query: Alg. 4's parts, then for each graph part the network
+// maps its selection features (log2 of its filter width and node size,
+// their ratio, log2 of the query width, parts - 1; the seven probe-state
+// inputs are 0) to y, and the part's beam is ef' = clamp(ceil(2^(y +
+// delta)), k, ef).  The weights (caller's layout) are staged once per
+// workgroup in LDS and read as broadcasts, so 256 queries share one copy
+// instead of every query reading all of them from the caches.  Writes the
+// features, y and ef' to feat_out when given; with no network only the
+// features.
+__global__ __launch_bounds__(256) void predict_beams_kernel(esgk::SearchArgs A,
+                                                            const float* __restrict__ params,
+                                                            int32_t* part_ef) {
   using namespace esgk;
-  __shared__ WaveLds stage[kWavesPerGroup];
-  const int lane = lane_id();
-  const int wave = (int)(threadIdx.x >> 6);
-  const int64_t qi = (int64_t)blockIdx.x * kWavesPerGroup + wave;
+  __shared__ float W[kMlpParams];
+  if (params)
+    for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) W[i] = params[i];
+  __syncthreads();
+  const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (qi >= A.nq) return;
   const int64_t lq = A.l[qi], rq = A.r[qi];
   int np = 0;
@@ -171,27 +184,50 @@ __global__ __launch_bounds__(256) void predict_beams_kernel(esgk::SearchArgs A, 
     if (p == 1 && np == 2) select_parts(A, lq, rq, 1, pt);
     int efp = A.ef;
     if (p < np && pt.kind == 1) {
-      const float f = lane < 5 ? probe_feature(lane, (float)(pt.y - pt.x + 1),
-                                               (float)(pt.b - pt.a + 1), rq - lq + 1, np, 0, 1,
-                                               0, A.k, 0, 0, 0.0f, 0.0f, 0.0f, 1.0f)
-                               : 0.0f;
+      const float wp = (float)(pt.y - pt.x + 1), L = (float)(pt.b - pt.a + 1);
+      float f[5];
+      f[0] = __log2f(wp);
+      f[1] = __log2f(L);
+      f[2] = wp / L;
+      f[3] = __log2f((float)(rq - lq + 1));
+      f[4] = (float)(np - 1);
       float y = 0.0f;
-      if (A.mlp) {
-        y = mlp_infer(A.mlp, f, &stage[wave], lane);
+      if (params) {
+        float x[kFeat];
+#pragma unroll
+        for (int i = 0; i < kFeat; i++)
+          x[i] = ((i < 5 ? f[i] : 0.0f) - W[kOffMu + i]) / W[kOffSd + i];
+        float h[kHidden];
+#pragma unroll
+        for (int j = 0; j < kHidden; j++) {
+          float a = W[kOffB1 + j];
+#pragma unroll
+          for (int i = 0; i < kFeat; i++) a = __builtin_fmaf(W[kOffW1 + j * kFeat + i], x[i], a);
+          h[j] = a > 0.0f ? a : 0.0f;
+          __builtin_amdgcn_sched_barrier(0);   // keeps the weight reads of one unit together
+        }
+        y = W[kOffB3];
+        for (int j = 0; j < kHidden; j++) {
+          float a = W[kOffB2 + j];
+#pragma unroll
+          for (int i = 0; i < kHidden; i++) {
+            a = __builtin_fmaf(W[kOffW2 + j * kHidden + i], h[i], a);
+            if ((i & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+          }
+          y = __builtin_fmaf(W[kOffW3 + j], a > 0.0f ? a : 0.0f, y);
+        }
         const float e2 = exp2f(y + A.mlp_delta);
         efp = e2 >= (float)A.ef ? A.ef : (int)ceilf(e2);
         efp = efp < A.k ? A.k : efp;
       }
       if (A.feat_out) {
         float* out = A.feat_out + (qi * 2 + p) * kFeatStride;
-        if (lane < kFeat) out[lane] = f;
-        if (lane == 0) {
-          out[kFeat] = y;
-          out[kFeat + 1] = (float)efp;
-        }
+        for (int i = 0; i < kFeat; i++) out[i] = i < 5 ? f[i] : 0.0f;
+        out[kFeat] = y;
+        out[kFeat + 1] = (float)efp;
       }
     }
-    if (lane == 0 && part_ef) part_ef[qi * 2 + p] = efp;
+    if (part_ef) part_ef[qi * 2 + p] = efp;
   }
 }
 
@@ -1059,7 +1095,6 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   if (predict) {
     if (o.mlp_target != 0) return ESG_EINVAL;   // a stopping step needs a probe
     if (nq > idx->res_queries) return ESG_ERANGE;
-    pa.mlp = a.mlp;
     pa.feat_out = o.feat_out;
     a.mlp = nullptr;
     a.feat_out = nullptr;
@@ -1071,13 +1106,13 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   const size_t lds = (size_t)esgk::kWavesPerGroup * (esgk::kStageBytes + 2 * (size_t)hash_cap);
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto sequence = [&](hipStream_t st) -> int32_t {
-    if (o.mlp) {
+    if (o.mlp && !predict) {
       mlp_pack_kernel<<<(esgk::kMlpParams + 255) / 256, 256, 0, st>>>(o.mlp, idx->mlp_pack);
       if (hipGetLastError() != hipSuccess) return ESG_EHIP;
     }
     if (predict && nq > 0) {
-      predict_beams_kernel<<<(unsigned)((nq + esgk::kWavesPerGroup - 1) / esgk::kWavesPerGroup),
-                             64 * esgk::kWavesPerGroup, 0, st>>>(pa, idx->part_ef);
+      predict_beams_kernel<<<(unsigned)((nq + 255) / 256), 256, 0, st>>>(pa, o.mlp,
+                                                                        idx->part_ef);
       if (hipGetLastError() != hipSuccess) return ESG_EHIP;
     }
     return o.router_threshold > 0 ? launch_routed(idx, a, fn, lds, o.router_threshold, mr, st)
