@@ -749,11 +749,19 @@ def main():
                                   skw.get("rerank", False))
     iw = torch.empty((nw, k), dtype=torch.int64, device=dev)
     dw = torch.empty((nw, k), dtype=torch.float32, device=dev)
+    tkw = skw
+    if skw.get("mlp") is not None and skw.get("probe_hops", 1) == 0:
+        # beams chosen before the search: time the search kernel alone, with
+        # the beams the predictor chose passed in (the predictor kernel is
+        # timed inside the step above, not here)
+        tkw = {kk: v for kk, v in skw.items() if kk not in ("mlp", "probe_hops", "mlp_delta",
+                                                             "mlp_target")}
+        tkw["part_ef"] = torch.from_numpy(m_part.astype(np.int32)).to(dev)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     for i in range(args.steps):
         starts[i].record()
-        ix.search_ex(Qw, lw, rw, k, ef, ids=iw, dists=dw, **skw)
+        ix.search_ex(Qw, lw, rw, k, ef, ids=iw, dists=dw, **tkw)
         ends[i].record()
     torch.cuda.synchronize()
     kern_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))

@@ -295,6 +295,12 @@ typedef struct {
   uint32_t* visited;     /* device [nq][2][visited_cap] or NULL: visited positions */
   int64_t visited_cap;   /* capacity per part of `visited`                  */
   int64_t* n_invalid;    /* device int64[1] or NULL: += invalid queries     */
+  const int32_t* part_ef;/* device int32 [nq][2] or NULL: the beam of each
+                            graph part (slot = the part's order), chosen by
+                            the caller (for instance from feat_out of an
+                            earlier call with probe_hops = 0); each part
+                            runs with m = cand_cap = clamp(value, k, ef);
+                            excludes mlp                                  */
 } esg_search_opts;
 
 /* Reserves the device workspace of the brute-force scan and the router:

@@ -77,7 +77,7 @@ class SearchOpts(ctypes.Structure):
                 ("feat_out", ctypes.c_void_p),
                 ("trace", ctypes.c_void_p),
                 ("visited", ctypes.c_void_p), ("visited_cap", ctypes.c_int64),
-                ("n_invalid", ctypes.c_void_p)]
+                ("n_invalid", ctypes.c_void_p), ("part_ef", ctypes.c_void_p)]
 
 
 class ScanOpts(ctypes.Structure):
@@ -257,7 +257,7 @@ class Index:
                   hop_budget: int = -1, router_threshold: int = 0, use_graph: bool = False,
                   scan_rerank: int = 0, mlp=None, probe_hops: int = 0, mlp_delta: float = 0.0,
                   mlp_target: int = 0, feat_out=None, trace=None, visited=None, visited_cap: int = 0,
-                  n_invalid=None, ids=None, dists=None, stream=None, opts="build"):
+                  n_invalid=None, part_ef=None, ids=None, dists=None, stream=None, opts="build"):
         import torch
         nq = queries.shape[0]
         dev = queries.device
@@ -281,7 +281,9 @@ class Index:
                            None if feat_out is None else feat_out.data_ptr(),
                            None if trace is None else trace.data_ptr(),
                            None if visited is None else visited.data_ptr(),
-                           visited_cap, None if n_invalid is None else n_invalid.data_ptr())
+                           visited_cap, None if n_invalid is None else n_invalid.data_ptr(),
+                           None if part_ef is None else
+                           _dev(part_ef, torch.int32, (nq, 2), "part_ef"))
             st = lib().esg_search_batch_ex(self._h, ctypes.byref(o), qp, lp, rp, nq, k, ef, ip, dp,
                                            _stream_ptr(stream))
         _check(st, "esg_search_batch")

@@ -1091,6 +1091,10 @@ int32_t esg_search_batch_ex(esg_index* idx, const esg_search_opts* opts, const f
   a.mlp_delta = o.mlp_delta;
   if (o.mlp_target < 0 || o.mlp_target > 1) return ESG_EINVAL;
   a.mlp_target = o.mlp_target;
+  if (o.part_ef) {
+    if (o.mlp) return ESG_EINVAL;
+    a.part_ef = o.part_ef;
+  }
   esgk::SearchArgs pa = a;   // the predictor's arguments
   if (predict) {
     if (o.mlp_target != 0) return ESG_EINVAL;   // a stopping step needs a probe

@@ -416,7 +416,8 @@ __device__ __forceinline__ void process_query(const SearchArgs& A, WaveLds* Ls, 
       pc.n_parts = np;
       pc.feat = A.feat_out ? A.feat_out + (qi * 2 + p) * kFeatStride : nullptr;
       // a beam chosen per part before the search (m = cand_cap = ef')
-      const int mp = A.part_ef ? A.part_ef[qi * 2 + p] : m;
+      const int pe = A.part_ef ? A.part_ef[qi * 2 + p] : m;
+      const int mp = pe < A.k ? A.k : (pe > m ? m : pe);
       const int cp = A.part_ef ? mp : cap_p;
       st = search_graph<KIND, G, CPL, E, LEARN>(A, Ls, V, pt, mp, cp, qr, Qp, dump, lane, pc);
       if constexpr (KIND != kF32)

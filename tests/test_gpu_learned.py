@@ -216,6 +216,18 @@ def test_learned_before_search_parity(tiny, delta):
         assert np.array_equal(ids[i], oid), i
         assert np.array_equal(dists[i].view(np.uint32), od.view(np.uint32)), i
     assert len(chosen) > 100 and len(set(chosen)) > 3    # the beams do vary per part
+    # the same beams passed in by the caller give the same answers; values
+    # outside [k, ef] are clamped
+    pe = np.where(np.isnan(F[:, :, 13]), ef_max, F[:, :, 13]).astype(np.int32)
+    ids2, dists2 = gix.search_ex(_t(Q), _t(l), _t(r), k, ef_max, part_ef=_t(pe))
+    torch.cuda.synchronize()
+    assert np.array_equal(ids2.cpu().numpy(), ids)
+    assert np.array_equal(dists2.cpu().numpy().view(np.uint32), dists.view(np.uint32))
+    big = np.full_like(pe, 10 * ef_max)
+    ids3, _ = gix.search_ex(_t(Q), _t(l), _t(r), k, ef_max, part_ef=_t(big))
+    ids4, _ = gix.search_ex(_t(Q), _t(l), _t(r), k, ef_max)
+    torch.cuda.synchronize()
+    assert np.array_equal(ids3.cpu().numpy(), ids4.cpu().numpy())
 
 
 @pytest.mark.parametrize("delta,probe", [(0.0, 4), (2.0, 8), (1.0, 1)])
