@@ -579,7 +579,10 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
     delete ix;
     return st;
   }
+  // the padding must be zero; the memset is asynchronous, so it completes
+  // before the rows are copied over it
   bool ok = hipMemset(ix->vec, 0, (size_t)h.n * ix->dp * 4) == hipSuccess &&
+            hipDeviceSynchronize() == hipSuccess &&
             hipMemcpy2D(ix->vec, (size_t)ix->dp * 4, vec.data(), (size_t)h.d * 4, (size_t)h.d * 4,
                         (size_t)h.n, hipMemcpyHostToDevice) == hipSuccess &&
             (adj.empty() ||
@@ -1370,6 +1373,7 @@ int32_t gpu_reset(GpuState* g, const float* X) {
   const bool ok =
       hipDeviceSynchronize() == hipSuccess &&
       hipMemset(ix.vec, 0, (size_t)ix.n * ix.dp * 4) == hipSuccess &&
+      hipDeviceSynchronize() == hipSuccess &&   // the padding's zeros land before the rows
       hipMemcpy2D(ix.vec, (size_t)ix.dp * 4, X, (size_t)ix.d * 4, (size_t)ix.d * 4, (size_t)ix.n,
                   hipMemcpyHostToDevice) == hipSuccess &&
       hipMemset(ix.adj, 0xFF, (size_t)ix.n_depth * ix.n * ix.R * 4) == hipSuccess &&   // ESG_NO_NODE
