@@ -52,9 +52,11 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 TARGET_RECALL = 0.95
 CAL_QUERIES = 50_000
 CAL_SE = 3.0          # calibration margin in standard errors of the mean recall
-# calibration grids: every ef up to 32 (one step is about 4 % of the work
-# there), and offsets delta in steps of 1/16 (2^(1/16): 4.4 % of beam)
-EF_GRID = list(range(10, 33)) + [36, 40, 48, 64, 96, 100, 112, 128, 192, 256, 384, 512, 768, 1024]
+# calibration grids: every ef up to 32, then steps of 4 to 64 and of 8 to
+# 128 (about 4-12 % of the work per step), and offsets delta in steps of
+# 1/16 (2^(1/16): 4.4 % of the beam)
+EF_GRID = (list(range(10, 33)) + list(range(36, 65, 4)) + list(range(72, 129, 8)) +
+           [160, 192, 224, 256, 320, 384, 512, 768, 1024])
 DELTA_GRID = [i / 16.0 for i in range(-16, 9)]
 LABEL_EF_GRID = [10, 12, 14, 16, 18, 20, 22, 24, 28, 32, 40, 48, 64, 96, 128, 192, 256]
 LABEL_HOP_GRID = [1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256]
@@ -348,7 +350,7 @@ def embedding_eval(args, dev):
     ix = esg.Index(path, 0)
     ix.add_storage("fp8")
     ix.add_storage("bf16")
-    ix.reserve(nq, 4_500_000)
+    ix.reserve(max(nq, 50_000), 4_500_000)
     info = ix.info()
     B = Bench(args, ix, w, wc, dev)
     # the exact scan's answers against float64 brute force on a sample
@@ -379,6 +381,33 @@ def embedding_eval(args, dev):
         kw = dict(traversal=trav, rerank=trav != "f32")
         ef, cal = B.pick([(e, lambda e=e: B.cal_recall(e, kw, with_se=True)) for e in efs])
         forms.append((B.evaluate(trav, ef, kw, cal), kw))
+    train_info = None
+    if not args.plain_only:
+        # learned beam width chosen before the search, FP8 + rerank, trained
+        # on traces of this shape's own training queries: a query's label is
+        # the smallest beam of the grid whose top 100 reaches recall 0.97
+        from paper_2504_04018_amd import learned
+        ntr = min(args.ntrain, 50_000)
+        wt = synth.make_workload(3, n=args.n, nq=ntr, query_stream=5000, range_stream=6000)
+        del wt["X"]
+        tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        Qt, lt, rt = tt(wt["Q"]), tt(wt["l"]), tt(wt["r"])
+        t1 = time.time()
+        _, gt_dt = learned.exact_answers(ix, Qt, lt, rt, k)
+        ef_max = 128
+        lkw = dict(traversal="fp8", rerank=True)
+        F, T = learned.traces(ix, Qt, lt, rt, k, [100, 104, 112, 120, 128], ef_max, 0, lkw, gt_dt,
+                              label_recall=0.97)
+        params, hist = learned.train(F, T)
+        train_info = dict(traces=int(F.shape[0]), queries=ntr, first_mse=round(hist[0], 4),
+                          final_mse=round(hist[-1], 4), seconds=round(time.time() - t1, 1))
+        log(f"learned (beams before the search): {train_info}")
+        del F, T, Qt, lt, rt, gt_dt
+        kw = dict(lkw, mlp=params, probe_hops=0)
+        dl, cal = B.pick([(dv, (lambda dv=dv: B.cal_recall(ef_max, dict(kw, mlp_delta=dv), True)))
+                          for dv in DELTA_GRID])
+        kw["mlp_delta"] = dl
+        forms.append((B.evaluate("learned_fp8", ef_max, kw, cal, delta=dl), kw))
     ok = [f for f in forms if f[0]["recall"] >= TARGET_RECALL]
     best, kw = max(ok or forms, key=lambda f: f[0]["qps"])
     ef = best["ef"]
@@ -405,19 +434,29 @@ def embedding_eval(args, dev):
         rel.append(np.abs(d_h[i][ok_].astype(np.float64) - d64) / np.maximum(d64, 1e-30))
     rel = np.concatenate(rel)
     dist_err = {"max_rel": float(rel.max()), "mean_rel": float(rel.mean()), "queries": len(rows)}
-    # roofline of the search kernel at the operating point
+    # roofline of the search kernel at the operating point (with a learned
+    # form, its beams passed in so that the search kernel is timed alone)
     tr = esg.trace_tensor(nq, dev)
-    ix.search_ex(Q, l, r, k, ef, trace=tr, **kw)
+    m_part = np.full((nq, 2), ef, np.int64)
+    tkw = kw
+    if kw.get("mlp") is not None:
+        feat = torch.full((nq, 2, 16), float("nan"), device=dev)
+        ix.search_ex(Q, l, r, k, ef, trace=tr, feat_out=feat, **kw)
+        fe = feat[:, :, 13].cpu().numpy()
+        m_part = np.where(np.isnan(fe), ef, fe).astype(np.int64)
+        tkw = {kk: v for kk, v in kw.items() if kk not in ("mlp", "probe_hops", "mlp_delta")}
+        tkw["part_ef"] = torch.from_numpy(m_part.astype(np.int32)).to(dev)
+    else:
+        ix.search_ex(Q, l, r, k, ef, trace=tr, **kw)
     torch.cuda.synchronize()
     trace = esg.decode_trace(tr)
     elem = {"bf16": 2.0, "fp8": 1.0 + 4.0 / d}.get(kw["traversal"], 4.0)
-    alg_bytes = algorithmic_bytes(trace, d, info["degree"], k, np.full((nq, 2), ef), elem,
-                                  kw["rerank"])
+    alg_bytes = algorithmic_bytes(trace, d, info["degree"], k, m_part, elem, kw["rerank"])
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
     for s_, e_ in ev:
         s_.record()
-        ix.search_ex(Q, l, r, k, ef, ids=ids, dists=dists, **kw)
+        ix.search_ex(Q, l, r, k, ef, ids=ids, dists=dists, **tkw)
         e_.record()
     torch.cuda.synchronize()
     kern_ms = float(np.mean([s_.elapsed_time(e_) for s_, e_ in ev]))
@@ -435,7 +474,7 @@ def embedding_eval(args, dev):
                    "fanout": info["fanout"], "leaf": info["leaf"], "degree": info["degree"],
                    "n_depth": info["n_depth"], "device_bytes": info["device_bytes"],
                    "index_build_s_device": None if build_s is None else round(build_s, 1),
-                   "gt_check": gt_check},
+                   "gt_check": gt_check, "delta": best.get("delta"), "training": train_info},
         "forms": [f[0] for f in forms],
         "sweep": B.sweep,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
