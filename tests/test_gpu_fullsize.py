@@ -101,6 +101,38 @@ def test_full_batch_learned_sampled_parity(deep):
     assert switched > SAMPLE // 2
 
 
+def test_full_batch_learned_before_search_sampled_parity(deep):
+    """The learned form the bench times (beams chosen before the search,
+    bfloat16 traversal + float32 rerank, ef cap 32) over the whole batch:
+    given the GPU's per-part beams, the oracle (its switch at hop 0)
+    reproduces the sampled answers bit for bit."""
+    w, gix, path = deep
+    Q, l, r = w["Q"], w["l"], w["r"]
+    nq = len(Q)
+    gix.reserve(nq, 262144)
+    rng = np.random.default_rng(13)
+    p = np.concatenate([rng.standard_normal(5056) * 0.15, [4.3],
+                        [14, 15, 0.6, 14, 0.3] + [0.0] * 7,          # feature means
+                        [3, 3, 0.3, 3, 0.5] + [1e-3] * 7]).astype(np.float32)
+    feat = torch.full((nq, 2, 16), float("nan"), device=DEV)
+    print("[gpu] full batch learned, beams before the search", flush=True)
+    ids, dists = gix.search_ex(_t(Q), _t(l), _t(r), 10, 32, traversal="bf16", rerank=True,
+                               mlp=_t(p), probe_hops=0, feat_out=feat)
+    torch.cuda.synchronize()
+    ids, dists, F = ids.cpu().numpy(), dists.cpu().numpy(), feat.cpu().numpy()
+    oix = oracle.read_index(path).with_bf16()
+    beams = set()
+    for i in _sample(nq, 14):
+        ef2 = np.where(np.isnan(F[i, :, 13]), 0, F[i, :, 13]).astype(np.int32)
+        beams.update(int(v) for v in ef2 if v > 0)
+        oid, od, _, st = oracle.query_learned(oix, Q[i], int(l[i]), int(r[i]), 10, 32, 0, ef2,
+                                              kind=oracle.DIST_BF16, rerank=1)
+        assert st == 0
+        assert np.array_equal(ids[i], oid), i
+        assert np.array_equal(dists[i].view(np.uint32), od.view(np.uint32)), i
+    assert len(beams) > 3
+
+
 def test_full_batch_scan_sampled(deep):
     """The exact scan over the whole 100,000-query batch, as the bench runs it
     for its recall judge: 64 sampled queries equal the oracle's float32 scan
