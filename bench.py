@@ -631,11 +631,15 @@ def main():
         # exact scan: algorithmic flops 2*w*d per query (in-range points only)
         wsum = float((width).sum().item())
         alg_flops = 2.0 * wsum * d
+        cap = 64 if k <= 32 else (128 if k <= 64 else 256)
+        mr, scan_table = autotune.tune_scan(ix, Q, l, r, k,
+                                            sorted({k, 2 * k, 4 * k, cap // 2, cap - 1}),
+                                            log=log)
         t_ms, nfb = [], 0
         for i in range(args.warmup + args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, _, nfb = ix.scan(Q, l, r, k)
+            _, _, nfb = ix.scan(Q, l, r, k, rerank_count=mr)
             torch.cuda.synchronize()
             if i >= args.warmup:
                 t_ms.append((time.perf_counter() - t0) * 1000.0)
@@ -645,7 +649,8 @@ def main():
                           "k": k, "ms_per_batch": round(ms, 3), "queries_per_s": round(nq / ms * 1e3),
                           "alg_tflop_per_batch": round(alg_flops / 1e12, 3),
                           "alg_tflops": round(tf, 1), "bf16_peak_tflops": MFMA_BF16_PEAK_TFLOPS,
-                          "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4), "n_fallback": int(nfb)}))
+                          "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4), "n_fallback": int(nfb),
+                          "rerank_count": mr, "tune": scan_table}))
         return
 
     def ef_candidates(kw):

@@ -5,9 +5,10 @@ caller-supplied measurement (so recall can come from held-out calibration
 queries while the throughput is timed on the batch itself).
 
 Knobs: LDS visited-hash capacity (waves per CU against spills to the global
-bitmap), router threshold (narrow ranges to the MFMA scan), and the
-beam-width calibration offset (or a fixed ef).  Every candidate runs the
-library's kernels; the tuner only measures.
+bitmap), router threshold (narrow ranges to the MFMA scan), the beam-width
+calibration offset (or a fixed ef), traversal storage, and the exact scan's
+rerank depth (``tune_scan``).  Every candidate runs the library's kernels;
+the tuner only measures.
 """
 from __future__ import annotations
 
@@ -70,3 +71,21 @@ def tune_settings(base_kw, grid, measure, target, log=None):
         best = max(((dict(base_kw, **{k_: r_[k_] for k_ in keys}), r_) for r_ in table),
                    key=lambda t: t[1]["recall"])
     return best[0], table
+
+
+def tune_scan(ix, Q, l, r, k, candidates, reps=3, log=None):
+    """The exact scan's rerank depth m_r: how many of a query's candidates
+    (bfloat16 MFMA order) are recomputed in float32 before the certificate.
+    A deeper rerank costs more per query but certifies more queries; an
+    uncertified query is rescanned exactly, so every m_r gives the same
+    answer and the fastest wins.  Returns (best m_r, table)."""
+    table = []
+    for mr in candidates:
+        sec = time_call(lambda: ix.scan(Q, l, r, k, rerank_count=mr), reps)
+        _, _, nfb = ix.scan(Q, l, r, k, rerank_count=mr)
+        row = dict(rerank_count=mr, ms=round(sec * 1e3, 3), n_fallback=int(nfb))
+        table.append(row)
+        if log:
+            log(f"tune scan {row}")
+    best = min(table, key=lambda t: t["ms"])
+    return best["rerank_count"], table
