@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void build_reverse_kernel(BuildArgs B) {
     const int len = __popcll(ballot(rv != kNoNode));
     if (len + cntc <= B.R) {
       uint64_t v = lane < cntc ? (uint64_t)src[lane] : kKeyInf;
-      v = sort32(v, lane);
+      v = sort32(v, lane, cntc);
       if (lane < cntc) row[len + lane] = (uint32_t)v;
     } else {
       const int m = len + cntc;

@@ -63,13 +63,15 @@ __device__ __forceinline__ uint32_t* wave_table(WaveLds* L) {
 
 template <int KIND>
 __device__ __forceinline__ uint4 load_chunk(const SearchArgs& A, uint32_t id, int ch) {
+  // row offset as one 32 x 32 -> 64-bit product (dp is positive)
+  const uint64_t row = (uint64_t)id * (uint32_t)A.dp;
   const uint4* p;
   if constexpr (KIND == kF32)
-    p = reinterpret_cast<const uint4*>(A.vec + (size_t)id * A.dp) + ch;
+    p = reinterpret_cast<const uint4*>(A.vec + row) + ch;
   else if constexpr (KIND == kBF16)
-    p = reinterpret_cast<const uint4*>(A.vec16 + (size_t)id * A.dp) + ch;
+    p = reinterpret_cast<const uint4*>(A.vec16 + row) + ch;
   else
-    p = reinterpret_cast<const uint4*>(A.vec8 + (size_t)id * A.dp) + ch;
+    p = reinterpret_cast<const uint4*>(A.vec8 + row) + ch;
   return *p;
 }
 
@@ -202,17 +204,20 @@ __device__ __forceinline__ float batch_dist(const SearchArgs& A, uint32_t nid, i
 
 // ---- ordered lists ------------------------------------------------------------
 
-// Ascending sort of the 32 keys in lanes 0..31 (bitonic network).
-__device__ __forceinline__ uint64_t sort32(uint64_t v, int lane) {
+// Ascending sort of the 32 keys in lanes 0..31 (bitonic network), of which
+// lanes n..31 hold +inf.  After the stage that sorts runs of k lanes, lanes
+// 0..k-1 form an ascending run; once k >= n that run holds every finite key
+// and the later stages would only move +inf keys, so they are skipped.
+__device__ __forceinline__ uint64_t sort32(uint64_t v, int lane, int n = 32) {
+  n = __builtin_amdgcn_readfirstlane(n);     // the same in every lane
 #pragma unroll
   for (int k = 2; k <= 32; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j >= 1; j >>= 1) {
-      uint64_t p = xor64(v, j, lane);
-      bool up = (lane & k) == 0;
-      bool lower = (lane & j) == 0;
-      v = (lower == up) ? kmin(v, p) : kmax(v, p);
+      // a lane keeps the larger key when exactly one of its bits j, k is set
+      v = cx64(v, j, lanes_with(j) ^ lanes_with(k), lane);
     }
+    if (k >= n) break;
   }
   return v;
 }
@@ -235,8 +240,7 @@ __device__ __forceinline__ void bitonic_finish(uint64_t (&L)[E], int cap, int la
   for (int s = 32; s >= 1; s >>= 1) {
 #pragma unroll
     for (int e = 0; e < E; e++) {
-      uint64_t p = xor64(L[e], s, lane);
-      L[e] = (lane & s) ? kmax(L[e], p) : kmin(L[e], p);
+      L[e] = cx64(L[e], s, lanes_with(s), lane);
     }
   }
 #pragma unroll

@@ -218,7 +218,7 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
         }
         return true;
       }
-      key = sort32(key, lane);
+      key = sort32(key, lane, n_new);
       const uint64_t kmin0 = readlane64(key, 0);
       u = kmin(p0, kmin0);                                       // min of P after the merge
       vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
@@ -326,7 +326,7 @@ __device__ __forceinline__ void scan_leaf(const SearchArgs& A, WaveLds* Ls, cons
       for (uint64_t mm = sm; mm; mm &= mm - 1)
         list_insert(R, readlane64(key, __builtin_ctzll(mm)), k, lane);
     } else if (sm != 0) {
-      key = sort32(key, lane);
+      key = sort32(key, lane, n_new);
       list_merge32(R, bperm64(key, 63 - lane), k, lane);
     }
     if (base > 0xFFFFFFFFu - kBatch) break;
@@ -351,7 +351,7 @@ __device__ __forceinline__ void rerank_f32(const SearchArgs& A, WaveLds* Ls, int
       const uint32_t nid = ok ? key_pos(kq) : kNoNode;
       const float bd = batch_dist<kF32, G32, CPL32>(A, nid, n_new, qr32, Ls, lane);
       uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
-      key = sort32(key, lane);
+      key = sort32(key, lane, n_new);
       list_merge32(R, bperm64(key, 63 - lane), k, lane);
     }
   }

@@ -59,25 +59,27 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Value held by lane ^ m (m a power of two below 64, a compile-time
-// constant after unrolling).  Xor 1 and 2 are DPP quad permutes, 4 and 8
-// DPP row shifts (lanes with the bit clear read lane+m, the others
-// lane-m), 16 a ds_swizzle inside each half wave, 32 a permlane32 swap.
+// constant after unrolling).  Xor 1 and 2 are DPP quad permutes; xor 4 is a
+// half-row mirror (lane ^ 7) followed by a quad reversal (^ 3), xor 8 a row
+// mirror (^ 15) followed by a half-row mirror (^ 7): two DPP moves and no
+// select; 16 is a ds_swizzle inside each half wave, 32 a permlane32 swap.
+// Every DPP source lane is inside the row, so the bound-control form (which
+// lets the compiler fold the move into the instruction that consumes it)
+// returns the same values.
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
 __device__ __forceinline__ uint32_t xor_u32(uint32_t v, int m, int lane) {
   switch (m) {
     case 1:
-      return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+      return (uint32_t)dpp<0xB1>((int)v);
     case 2:
-      return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
-    case 4: {
-      uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x104, 0xF, 0xF, false);
-      uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x114, 0xF, 0xF, false);
-      return (lane & 4) ? dn : up;
-    }
-    case 8: {
-      uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x108, 0xF, 0xF, false);
-      uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x118, 0xF, 0xF, false);
-      return (lane & 8) ? dn : up;
-    }
+      return (uint32_t)dpp<0x4E>((int)v);
+    case 4:
+      return (uint32_t)dpp<0x1B>(dpp<0x141>((int)v));
+    case 8:
+      return (uint32_t)dpp<0x141>(dpp<0x140>((int)v));
     case 16:
       return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);
     default: {
@@ -109,6 +111,31 @@ __device__ __forceinline__ uint64_t prev_lane64(uint64_t v) {
   uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, 0x138, 0xF, 0xF, false);
   uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), 0x138, 0xF, 0xF, false);
   return ((uint64_t)hi << 32) | lo;
+}
+
+// The lanes whose index has bit b set (b a power of two), as a lane mask.
+constexpr uint64_t lanes_with(int b) {
+  return b == 1    ? 0xAAAAAAAAAAAAAAAAull
+         : b == 2  ? 0xCCCCCCCCCCCCCCCCull
+         : b == 4  ? 0xF0F0F0F0F0F0F0F0ull
+         : b == 8  ? 0xFF00FF00FF00FF00ull
+         : b == 16 ? 0xFFFF0000FFFF0000ull
+         : b == 32 ? 0xFFFFFFFF00000000ull
+                   : 0ull;
+}
+
+// One compare-exchange step of a sorting network with the partner lane ^ j:
+// lanes in the mask keep_max keep the larger of the two keys, the others
+// the smaller.  One comparison; the direction is applied to its lane mask
+// by a scalar xor.  Equal keys are equal values, so either choice is the
+// same result.
+__device__ __forceinline__ uint64_t cx64(uint64_t v, int j, uint64_t keep_max, int lane) {
+  const uint64_t p = xor64(v, j, lane);
+  return __builtin_amdgcn_inverse_ballot_w64(ballot(v > p) ^ keep_max) ? p : v;
+}
+__device__ __forceinline__ uint32_t cx32(uint32_t v, int j, uint64_t keep_max, int lane) {
+  const uint32_t p = xor_u32(v, j, lane);
+  return __builtin_amdgcn_inverse_ballot_w64(ballot(v > p) ^ keep_max) ? p : v;
 }
 
 __device__ __forceinline__ uint64_t kmin(uint64_t a, uint64_t b) { return a < b ? a : b; }
