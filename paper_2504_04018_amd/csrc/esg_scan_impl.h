@@ -366,7 +366,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(ScanArgs S) {
       const float bd = batch_dist<kF32, G32, CPL32>(A, nid, n_new, qr32, Ls, lane);
       uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
       key = sort32(key, lane, n_new);
-      list_merge32(R, bperm64(key, 63 - lane), k, lane);
+      merge_sorted32(R, key, k, lane);
     }
   }
   // certification

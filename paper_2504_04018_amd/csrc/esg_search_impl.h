@@ -176,7 +176,7 @@ __device__ __forceinline__ float batch_dist(const SearchArgs& A, uint32_t nid, i
       int nv = TG;
 #pragma unroll
       for (int s = 1; s < TG; s <<= 1) {
-        const bool upper = (lane & s) != 0;
+        const bool upper = lane_in(lanes_with(s));
         nv >>= 1;
 #pragma unroll
         for (int i = 0; i < TG / 2; i++) {
@@ -189,7 +189,8 @@ __device__ __forceinline__ float batch_dist(const SearchArgs& A, uint32_t nid, i
       }
 #pragma unroll
       for (int s = TG; s < G; s <<= 1) acc[0] = acc[0] + xor_f(acc[0], s, lane);
-      if (t < TG) {
+      constexpr uint64_t kLead = lanes_mod_below(G, TG);   // the lanes with t < TG
+      if (lane_in(kLead)) {
         int r = 0;
 #pragma unroll
         for (int s = 1, h = TG >> 1; s < TG; s <<= 1, h >>= 1) r += (t & s) ? h : 0;
@@ -256,6 +257,29 @@ __device__ __forceinline__ void list_merge32(uint64_t (&L)[E], uint64_t brev, in
   bitonic_finish<E>(L, cap, lane);
 }
 
+// A one-register list that keeps at most 32 keys (lanes 32..63 hold +inf)
+// takes up to 32 sorted keys `rev` given reversed in lanes 0..31 (lane 31-j
+// = j-th smallest, +inf elsewhere) within the low half wave: lane i <
+// 32 holding min(L[i], rev[i]) is a bitonic sequence of the 32 smallest keys
+// of both, which five half-wave steps sort; the cross-half step of the full
+// merge is not needed.
+__device__ __forceinline__ void merge_low32(uint64_t& L, uint64_t rev, int cap, int lane) {
+  L = kmin(L, rev);
+#pragma unroll
+  for (int s = 16; s >= 1; s >>= 1) L = cx64(L, s, lanes_with(s), lane);
+  if (lane >= cap) L = kKeyInf;
+}
+
+// Merges up to 32 keys sorted ascending in lanes 0..31 (+inf elsewhere)
+// into the sorted list.
+template <int E>
+__device__ __forceinline__ void merge_sorted32(uint64_t (&L)[E], uint64_t key, int cap, int lane) {
+  if (E == 1 && cap <= 32)
+    merge_low32(L[0], bperm64(key, (31 - lane) & 63), cap, lane);
+  else
+    list_merge32(L, bperm64(key, 63 - lane), cap, lane);
+}
+
 // Merges two sorted lists of the same shape into the first.
 template <int E>
 __device__ __forceinline__ void list_merge(uint64_t (&A)[E], const uint64_t (&B)[E], int cap,
@@ -272,7 +296,7 @@ __device__ __forceinline__ void list_pop(uint64_t (&L)[E], int lane) {
   for (int e = 0; e < E; e++) {
     uint64_t nxt = (e + 1 < E) ? readlane64(L[e + 1 < E ? e + 1 : e], 0) : kKeyInf;
     uint64_t sh = next_lane64(L[e]);
-    L[e] = lane == 63 ? nxt : sh;
+    L[e] = lane_in(1ull << 63) ? nxt : sh;
   }
 }
 
@@ -288,7 +312,7 @@ __device__ __forceinline__ void list_insert(uint64_t (&L)[E], uint64_t key, int 
   for (int e = 0; e < E; e++) {
     const uint64_t last = readlane64(L[e], 63);
     uint64_t prev = prev_lane64(L[e]);
-    prev = lane == 0 ? carry : prev;
+    prev = lane_in(1ull) ? carry : prev;
     const int i = e * kWave + lane;
     L[e] = i < rank ? L[e] : (i == rank ? key : prev);
     if (i >= cap) L[e] = kKeyInf;

@@ -152,10 +152,14 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
     if (ep >= pt.x && ep <= pt.y) Q[0] = kep;
   }
   if (dump && lane == 0 && A.visited_cap > 0) dump[0] = ep;
-  int64_t nvis = 1, hops = 0;
-  int64_t n_inr = (ep >= pt.x && ep <= pt.y) ? 1 : 0;   // visited points inside [x,y]
+  // 32-bit counters (a part visits at most its n < 2^32 positions) keep
+  // the scalar registers of the hop loop few
+  uint32_t nvis = 1, hops = 0;
+  uint32_t n_inr = (ep >= pt.x && ep <= pt.y) ? 1 : 0;  // visited points inside [x,y]
   const float d_ep = key_dist(kep);
-  int64_t hop_limit = A.hop_budget;                         // < 0: unbounded
+  // expansions allowed (hop_budget < 0: unbounded, kept as 2^32 - 1)
+  uint32_t hop_limit = (A.hop_budget < 0 || A.hop_budget > 0xFFFFFFFFll)
+                           ? 0xFFFFFFFFu : (uint32_t)A.hop_budget;
 
   // The row of the next candidate is fetched as soon as that candidate is
   // known (right after the new batch is sorted), so the load overlaps the
@@ -167,10 +171,10 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
   auto hop = [&](bool probe_phase) -> bool {
     {
       if (u == kKeyInf) return false;                            // P is empty
-      if (probe_phase && hops == A.probe_hops) return false;    // probe over: switch first
+      if (probe_phase && hops == (uint32_t)A.probe_hops) return false;  // probe over: switch first
       const uint64_t worst = list_at(Q, m - 1);
       if (worst != kKeyInf && worst < u) return false;           // farther than a full Q
-      if (hop_limit >= 0 && hops >= hop_limit) return false;
+      if (hops >= hop_limit) return false;
       list_pop(P, lane);
       hops++;
 
@@ -186,7 +190,9 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
       if (is_new) Ls->ids[rank_below(nm)] = v;
       wave_lds_sync();
       const uint32_t nid = lane < n_new ? Ls->ids[lane] : kNoNode;
-      if (dump && lane < n_new && nvis + lane < A.visited_cap) dump[nvis + lane] = nid;
+      if (__builtin_expect(dump != nullptr, 0)) {   // a uniform branch: the test is not folded
+        if (lane < n_new && (int64_t)nvis + lane < A.visited_cap) dump[nvis + lane] = nid;
+      }
       nvis += n_new;
       if (probe_phase) n_inr += __popcll(ballot(lane < n_new && nid >= pt.x && nid <= pt.y));
 
@@ -222,16 +228,22 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
       const uint64_t kmin0 = readlane64(key, 0);
       u = kmin(p0, kmin0);                                       // min of P after the merge
       vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
-      list_merge32(P, bperm64(key, 63 - lane), cap_p, lane);
+      merge_sorted32(P, key, cap_p, lane);
       const uint32_t kp = key_pos(key);
-      const bool inr = lane < kBatch && key != kKeyInf && kp >= pt.x && kp <= pt.y;
+      const bool inr = lane_in(0xFFFFFFFFull) && key != kKeyInf && kp >= pt.x && kp <= pt.y;
       const uint64_t qm = ballot(inr);
       if (qm != 0) {
+        // the in-range keys, reversed into lanes 31, 30, ... (a list of at
+        // most 32) or 63, 62, ...
+        const bool low = E == 1 && m <= 32;
         Ls->stage[lane] = kKeyInf;
         wave_lds_sync();
-        if (inr) Ls->stage[63 - rank_below(qm)] = key;
+        if (inr) Ls->stage[(low ? 31 : 63) - rank_below(qm)] = key;
         wave_lds_sync();
-        list_merge32(Q, Ls->stage[lane], m, lane);
+        if (low)
+          merge_low32(Q[0], Ls->stage[lane], m, lane);
+        else
+          list_merge32(Q, Ls->stage[lane], m, lane);
       }
     }
     return true;
@@ -253,7 +265,7 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
   // prune leaves unchanged.
   constexpr bool kLearned = LEARN == 1 || LEARN == 2;
   const uint64_t worst0 = (kLearned && go) ? list_at(Q, m - 1) : kKeyInf;
-  if (kLearned && go && u != kKeyInf && hops == A.probe_hops && !(worst0 < u)) {
+  if (kLearned && go && u != kKeyInf && hops == (uint32_t)A.probe_hops && !(worst0 < u)) {
     // probe over: features -> predicted beam width or stopping step
     int qsize = 0, psize = 0;
 #pragma unroll
@@ -276,7 +288,7 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
         // stopping step: the part may take ceil(2^(y + delta)) more expansions
         const int64_t more = e2 >= 1.0e9f ? (int64_t)1000000000
                                           : (int64_t)ceilf(e2 < 1.0f ? 1.0f : e2);
-        if (hop_limit < 0 || hops + more < hop_limit) hop_limit = hops + more;
+        if ((int64_t)hops + more < (int64_t)hop_limit) hop_limit = (uint32_t)(hops + more);
         efp = (int)more;
       } else {
         efp = e2 >= (float)m ? m : (int)ceilf(e2);
@@ -327,7 +339,7 @@ __device__ __forceinline__ void scan_leaf(const SearchArgs& A, WaveLds* Ls, cons
         list_insert(R, readlane64(key, __builtin_ctzll(mm)), k, lane);
     } else if (sm != 0) {
       key = sort32(key, lane, n_new);
-      list_merge32(R, bperm64(key, 63 - lane), k, lane);
+      merge_sorted32(R, key, k, lane);
     }
     if (base > 0xFFFFFFFFu - kBatch) break;
   }
@@ -352,7 +364,7 @@ __device__ __forceinline__ void rerank_f32(const SearchArgs& A, WaveLds* Ls, int
       const float bd = batch_dist<kF32, G32, CPL32>(A, nid, n_new, qr32, Ls, lane);
       uint64_t key = lane < n_new ? make_key(bd, nid) : kKeyInf;
       key = sort32(key, lane, n_new);
-      list_merge32(R, bperm64(key, 63 - lane), k, lane);
+      merge_sorted32(R, key, k, lane);
     }
   }
 #pragma unroll

@@ -124,6 +124,22 @@ constexpr uint64_t lanes_with(int b) {
                    : 0ull;
 }
 
+// Lanes l with l mod g < n, as a lane mask (g a power of two).
+constexpr uint64_t lanes_mod_below(int g, int n) {
+  uint64_t m = 0;
+  for (int l = 0; l < kWave; l++)
+    if (l % g < n) m |= 1ull << l;
+  return m;
+}
+
+// True in the lanes of a lane mask.  With a compile-time mask the test costs
+// no vector instruction and holds no register (the constant is rebuilt where
+// it is needed), unlike a comparison of the lane index, which the compiler
+// hoists out of every loop into a register pair.
+__device__ __forceinline__ bool lane_in(uint64_t mask) {
+  return __builtin_amdgcn_inverse_ballot_w64(mask);
+}
+
 // One compare-exchange step of a sorting network with the partner lane ^ j:
 // lanes in the mask keep_max keep the larger of the two keys, the others
 // the smaller.  One comparison; the direction is applied to its lane mask
