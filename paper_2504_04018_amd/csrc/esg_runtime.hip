@@ -5,7 +5,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/esg.h"
@@ -454,6 +456,106 @@ int width_index(int cap) {
   return 4;
 }
 
+// Host-to-device copies of index data go through a pinned staging buffer
+// that the library allocates once (hipHostMalloc) and keeps: large copies
+// straight from pageable memory have left device data that did not match
+// its source (seen right after a device build in the same process, under
+// the kernel tracer).  Rows of `width` bytes (source pitch spitch) land in
+// device rows of dpitch bytes whose tail is zero-filled in the staging
+// buffer.  Synchronous; false on a HIP error.
+std::mutex g_stage_mu;
+char* g_stage = nullptr;
+constexpr size_t kStagingBytes = (size_t)64 << 20;
+
+bool h2d_rows(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width,
+              size_t rows) {
+  if (rows == 0 || width == 0) return true;
+  std::lock_guard<std::mutex> lock(g_stage_mu);
+  if (!g_stage && hipHostMalloc((void**)&g_stage, kStagingBytes, hipHostMallocDefault) != hipSuccess) {
+    g_stage = nullptr;
+    return false;
+  }
+  if (dpitch > kStagingBytes) return false;
+  const size_t per = kStagingBytes / dpitch;   // rows per chunk
+  for (size_t r0 = 0; r0 < rows; r0 += per) {
+    const size_t nr = std::min(per, rows - r0);
+    for (size_t r = 0; r < nr; r++) {
+      std::memcpy(g_stage + r * dpitch, static_cast<const char*>(src) + (r0 + r) * spitch, width);
+      if (dpitch > width) std::memset(g_stage + r * dpitch + width, 0, dpitch - width);
+    }
+    if (hipMemcpy(static_cast<char*>(dst) + r0 * dpitch, g_stage, nr * dpitch,
+                  hipMemcpyHostToDevice) != hipSuccess)
+      return false;
+  }
+  return true;
+}
+
+bool h2d(void* dst, const void* src, size_t bytes) {
+  const size_t chunk = (size_t)1 << 20;   // rows of 1 MB and a last row with the rest
+  const size_t full = bytes / chunk, rest = bytes - full * chunk;
+  const char* s = static_cast<const char*>(src) + full * chunk;
+  return h2d_rows(dst, chunk, src, chunk, chunk, full) &&
+         h2d_rows(static_cast<char*>(dst) + full * chunk, rest, s, rest, rest, rest ? 1 : 0);
+}
+
+// Checksum of an upload: the 64-bit sum over words i of mix(i, word i),
+// order-independent, so the device adds it up in any order.
+__host__ __device__ inline uint64_t mix_word(uint64_t i, uint32_t w) {
+  uint64_t x = ((uint64_t)w | (i << 32)) ^ (i >> 32);
+  x *= 0x9E3779B97F4A7C15ull;
+  return x ^ (x >> 29);
+}
+
+__global__ void checksum_kernel(const uint32_t* __restrict__ p, uint64_t n,
+                                unsigned long long* __restrict__ out) {
+  uint64_t s = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    s += mix_word(i, p[i]);
+  __shared__ unsigned long long part[256];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (unsigned w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, part[0]);
+}
+
+// Compares a device copy with its host source: rows of `width` 32-bit words
+// on the host land in device rows of `pitch` words whose tail is zero.
+// Returns 1 when they match, 0 when they differ, -1 on a HIP error.
+int verify_upload(const void* dev, const void* host, int64_t rows, int64_t width, int64_t pitch) {
+  const uint32_t* h = static_cast<const uint32_t*>(host);
+  const int nt = 8;
+  uint64_t part[nt] = {0};
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; t++)
+    th.emplace_back([&, t] {
+      uint64_t s = 0;
+      for (int64_t r = rows * t / nt; r < rows * (t + 1) / nt; r++)
+        for (int64_t j = 0; j < pitch; j++)
+          s += mix_word((uint64_t)(r * pitch + j), j < width ? h[r * width + j] : 0u);
+      part[t] = s;
+    });
+  for (auto& x : th) x.join();
+  uint64_t want = 0;
+  for (int t = 0; t < nt; t++) want += part[t];
+  unsigned long long* d = nullptr;
+  unsigned long long got = 0;
+  const bool ok = hipMalloc((void**)&d, 8) == hipSuccess && hipMemset(d, 0, 8) == hipSuccess &&
+                  (checksum_kernel<<<1024, 256>>>(static_cast<const uint32_t*>(dev),
+                                                  (uint64_t)(rows * pitch), d),
+                   hipGetLastError() == hipSuccess) &&
+                  hipMemcpy(&got, d, 8, hipMemcpyDeviceToHost) == hipSuccess;
+  if (d) (void)hipFree(d);
+  if (!ok) {
+    (void)hipGetLastError();
+    return -1;
+  }
+  return got == want ? 1 : 0;
+}
+
 int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
   FILE* f = fopen(path, "rb");
   if (!f) return ESG_EIO;
@@ -579,22 +681,38 @@ int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
     delete ix;
     return st;
   }
-  // the padding must be zero; the memset is asynchronous, so it completes
-  // before the rows are copied over it
-  bool ok = hipMemset(ix->vec, 0, (size_t)h.n * ix->dp * 4) == hipSuccess &&
-            hipDeviceSynchronize() == hipSuccess &&
-            hipMemcpy2D(ix->vec, (size_t)ix->dp * 4, vec.data(), (size_t)h.d * 4, (size_t)h.d * 4,
-                        (size_t)h.n, hipMemcpyHostToDevice) == hipSuccess &&
-            (adj.empty() ||
-             hipMemcpy(ix->adj, adj.data(), adj.size() * 4, hipMemcpyHostToDevice) == hipSuccess) &&
-            hipMemcpy(ix->ep, ep.data(), ep.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
-            (row_base.empty() || hipMemcpy(ix->row_base, row_base.data(), row_base.size() * 8,
-                                           hipMemcpyHostToDevice) == hipSuccess) &&
-            hipMemcpy(ix->ext_id, ids.data(), ids.size() * 8, hipMemcpyHostToDevice) ==
-                hipSuccess &&
-            hipMemset(ix->counter, 0, 256) == hipSuccess &&
-            hipMemset(ix->spill, 0, spill_bytes) == hipSuccess &&   // bitmaps start all zero
-            hipDeviceSynchronize() == hipSuccess;
+  // rows are padded with zeros to dp values on the way
+  auto upload = [&]() {
+    return h2d_rows(ix->vec, (size_t)ix->dp * 4, vec.data(), (size_t)h.d * 4, (size_t)h.d * 4,
+                    (size_t)h.n) &&
+           h2d(ix->adj, adj.data(), adj.size() * 4) && h2d(ix->ep, ep.data(), ep.size() * 4) &&
+           h2d(ix->row_base, row_base.data(), row_base.size() * 8) &&
+           h2d(ix->ext_id, ids.data(), ids.size() * 8) &&
+           hipMemset(ix->counter, 0, 256) == hipSuccess &&
+           hipMemset(ix->spill, 0, spill_bytes) == hipSuccess &&   // bitmaps start all zero
+           hipDeviceSynchronize() == hipSuccess;
+  };
+  // The device copies of the vectors and the adjacency are checked against
+  // the (checksummed) file contents once everything is in place; a copy
+  // that differs is made again once, and a second difference is an error.
+  auto verified = [&]() {
+    const int v = verify_upload(ix->vec, vec.data(), h.n, h.d, ix->dp);
+    const int a = adj.empty() ? 1
+                              : verify_upload(ix->adj, adj.data(), (int64_t)adj.size() / h.degree,
+                                              h.degree, h.degree);
+    return v < 0 || a < 0 ? -1 : (v == 1 && a == 1 ? 1 : 0);
+  };
+  bool ok = upload();
+  int check = ok ? verified() : -1;
+  if (check == 0) {
+    std::fprintf(stderr, "esg_load_index: the device copy of %s differs from the file; copying "
+                 "again\n", path);
+    ok = upload();
+    check = ok ? verified() : -1;
+    if (check == 0)
+      std::fprintf(stderr, "esg_load_index: the device copy of %s differs again\n", path);
+  }
+  ok = ok && check == 1;
   if (!ok) {
     (void)hipGetLastError();
     ix->release();
@@ -1372,14 +1490,17 @@ int32_t gpu_reset(GpuState* g, const float* X) {
   if (hipSetDevice(ix.device) != hipSuccess) return ESG_EHIP;
   const bool ok =
       hipDeviceSynchronize() == hipSuccess &&
-      hipMemset(ix.vec, 0, (size_t)ix.n * ix.dp * 4) == hipSuccess &&
-      hipDeviceSynchronize() == hipSuccess &&   // the padding's zeros land before the rows
-      hipMemcpy2D(ix.vec, (size_t)ix.dp * 4, X, (size_t)ix.d * 4, (size_t)ix.d * 4, (size_t)ix.n,
-                  hipMemcpyHostToDevice) == hipSuccess &&
+      h2d_rows(ix.vec, (size_t)ix.dp * 4, X, (size_t)ix.d * 4, (size_t)ix.d * 4, (size_t)ix.n) &&
       hipMemset(ix.adj, 0xFF, (size_t)ix.n_depth * ix.n * ix.R * 4) == hipSuccess &&   // ESG_NO_NODE
       hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
+    return ESG_EHIP;
+  }
+  // the rows on the device are checked against X (as the loader checks its copy)
+  const int v = verify_upload(ix.vec, X, ix.n, ix.d, ix.dp);
+  if (v != 1) {
+    if (v == 0) std::fprintf(stderr, "esg builder: the device copy of the vectors differs\n");
     return ESG_EHIP;
   }
   return ESG_OK;
@@ -1418,8 +1539,7 @@ int32_t gpu_put_rows(GpuState* g, int32_t depth, const uint32_t* rows) {
   if (!g || !rows || depth < 0 || depth >= g->ix.n_depth) return ESG_EINVAL;
   esg_index& ix = g->ix;
   if (hipSetDevice(ix.device) != hipSuccess) return ESG_EHIP;
-  if (hipMemcpy(ix.adj + (size_t)depth * ix.n * ix.R, rows, (size_t)ix.n * ix.R * 4,
-                hipMemcpyHostToDevice) != hipSuccess ||
+  if (!h2d(ix.adj + (size_t)depth * ix.n * ix.R, rows, (size_t)ix.n * ix.R * 4) ||
       hipDeviceSynchronize() != hipSuccess) {
     (void)hipGetLastError();
     return ESG_EHIP;

@@ -151,7 +151,6 @@ template <int NK, int E, int TP, int DP>
 __global__ __launch_bounds__(256) void scan_select_kernel(ScanArgs S) {
   constexpr int ROW = DP + 8;                  // padded LDS row (bf16 elements)
   constexpr int NWG = 4 * kScanWinPerWave;     // windows per workgroup
-  constexpr int CAP = 64 * E;                  // list length per window
   __shared__ __align__(16) uint16_t tile[TP * ROW];
   __shared__ float tnorm[TP];
   constexpr int BUF = DP >= 1024 ? 96 : kScanBuf;   // keeps the LDS footprint under 64 KB
