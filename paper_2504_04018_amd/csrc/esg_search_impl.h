@@ -397,26 +397,23 @@ __device__ __forceinline__ bool visit(const SearchArgs& A, Visited& V, uint32_t 
     const uint32_t home = x >> V.shift;
     const uint32_t low = x & ((1u << V.shift) - 1u);
     const uint32_t tmask = (uint32_t)A.hash_cap - 1u;
-    uint16_t* slots = reinterpret_cast<uint16_t*>(V.table);
     overflow = true;
     for (uint32_t j = 0; j < 8u; j++) {
       const uint32_t s = (home + j) & tmask;
       const uint32_t want = 0x8000u | (j << 12) | low;
-      uint32_t e = slots[s];
-      if (e == 0u) {
-        // claim the empty slot with a CAS on its 32-bit word
-        uint32_t* word = V.table + (s >> 1);
-        const uint32_t sh = (s & 1u) * 16u;
-        uint32_t old = *word;
-        for (;;) {
-          const uint32_t cur = (old >> sh) & 0xFFFFu;
-          if (cur != 0u) { e = cur; break; }
-          const uint32_t got = atomicCAS(word, old, old | (want << sh));
-          if (got == old) { e = 0u; break; }
-          old = got;
-        }
-        if (e == 0u) { is_new = true; overflow = false; break; }
+      // one read of the slot's 32-bit word; an empty slot is claimed with a
+      // CAS on that word (another lane may take either half meanwhile)
+      uint32_t* word = V.table + (s >> 1);
+      const uint32_t sh = (s & 1u) * 16u;
+      uint32_t old = *word;
+      uint32_t e = (old >> sh) & 0xFFFFu;
+      while (e == 0u) {
+        const uint32_t got = atomicCAS(word, old, old | (want << sh));
+        if (got == old) break;
+        old = got;
+        e = (old >> sh) & 0xFFFFu;
       }
+      if (e == 0u) { is_new = true; overflow = false; break; }
       if (e == want) { overflow = false; break; }   // already visited
     }
   }

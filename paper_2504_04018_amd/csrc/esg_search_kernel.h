@@ -187,9 +187,11 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
         vrow = (lane < A.R && u != kKeyInf) ? rows[(size_t)key_pos(u) * A.R + lane] : kNoNode;
         return true;
       }
-      if (is_new) Ls->ids[rank_below(nm)] = v;
-      wave_lds_sync();
-      const uint32_t nid = lane < n_new ? Ls->ids[lane] : kNoNode;
+      // the new ids to lanes 0..n_new-1 in lane order (the others fill the
+      // remaining lanes, so the push is a permutation)
+      const int rn = rank_below(nm);
+      const uint32_t pushed = push(v, is_new ? rn : n_new + (lane - rn));
+      const uint32_t nid = lane < n_new ? pushed : kNoNode;
       if (__builtin_expect(dump != nullptr, 0)) {   // a uniform branch: the test is not folded
         if (lane < n_new && (int64_t)nvis + lane < A.visited_cap) dump[nvis + lane] = nid;
       }
@@ -235,15 +237,17 @@ __device__ __forceinline__ PartStats search_graph(const SearchArgs& A, WaveLds* 
       if (qm != 0) {
         // the in-range keys, reversed into lanes 31, 30, ... (a list of at
         // most 32) or 63, 62, ...
+        // (one permutation: the other lanes fill lanes 0..top-nq and
+        // top+1..63 with +inf)
         const bool low = E == 1 && m <= 32;
-        Ls->stage[lane] = kKeyInf;
-        wave_lds_sync();
-        if (inr) Ls->stage[(low ? 31 : 63) - rank_below(qm)] = key;
-        wave_lds_sync();
+        const int top = low ? 31 : 63, nq = __popcll(qm), rq = rank_below(qm);
+        const int ro = lane - rq;
+        const int dst = inr ? top - rq : (ro <= top - nq ? ro : ro + nq);
+        const uint64_t rev = push64(inr ? key : kKeyInf, dst);
         if (low)
-          merge_low32(Q[0], Ls->stage[lane], m, lane);
+          merge_low32(Q[0], rev, m, lane);
         else
-          list_merge32(Q, Ls->stage[lane], m, lane);
+          list_merge32(Q, rev, m, lane);
       }
     }
     return true;

@@ -34,6 +34,19 @@ __device__ __forceinline__ uint64_t bperm64(uint64_t v, int src_lane) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Forward permute: lane i's value lands in lane dst(i).  The destinations
+// must form a permutation of the 64 lanes and every lane must be active,
+// so that each lane is written exactly once.
+__device__ __forceinline__ uint32_t push(uint32_t v, int dst) {
+  return (uint32_t)__builtin_amdgcn_ds_permute(dst << 2, (int)v);
+}
+
+__device__ __forceinline__ uint64_t push64(uint64_t v, int dst) {
+  const uint32_t lo = push((uint32_t)v, dst);
+  const uint32_t hi = push((uint32_t)(v >> 32), dst);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint32_t readlane(uint32_t v, int lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
