@@ -135,13 +135,14 @@ def algorithmic_bytes(trace, d, R, k, m, elem_bytes, rerank):
 
 
 def kernel_sources_sha256():
-    """Hash of the library's kernel sources: a stored traffic figure is used
-    only while these are unchanged."""
+    """Hash of the sources the search kernels are compiled from (the
+    headers and the per-dimension instantiation unit): a stored traffic
+    figure is used only while these are unchanged."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2504_04018_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".h", ".hip")):
+        if f.endswith(".h") or f == "esg_search_inst.hip":
             h.update(f.encode())
             h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()

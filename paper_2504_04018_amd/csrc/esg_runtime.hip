@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -522,10 +523,21 @@ __global__ void checksum_kernel(const uint32_t* __restrict__ p, uint64_t n,
   if (threadIdx.x == 0) atomicAdd(out, part[0]);
 }
 
+// Test hook: ESG_FAULT_UPLOAD_CHECK=n makes the n-th upload check (1-based,
+// counted per process) report a difference, =all every check.
+std::atomic<int64_t> g_check_count{0};
+
+bool upload_check_forced() {
+  const int64_t c = ++g_check_count;
+  const char* env = std::getenv("ESG_FAULT_UPLOAD_CHECK");
+  return env && (std::strcmp(env, "all") == 0 || std::atoll(env) == c);
+}
+
 // Compares a device copy with its host source: rows of `width` 32-bit words
 // on the host land in device rows of `pitch` words whose tail is zero.
 // Returns 1 when they match, 0 when they differ, -1 on a HIP error.
 int verify_upload(const void* dev, const void* host, int64_t rows, int64_t width, int64_t pitch) {
+  const bool forced = upload_check_forced();
   const uint32_t* h = static_cast<const uint32_t*>(host);
   const int nt = 8;
   uint64_t part[nt] = {0};
@@ -553,7 +565,7 @@ int verify_upload(const void* dev, const void* host, int64_t rows, int64_t width
     (void)hipGetLastError();
     return -1;
   }
-  return got == want ? 1 : 0;
+  return got == want && !forced ? 1 : 0;
 }
 
 int32_t load_impl(const char* path, int32_t hip_device, esg_index** out) {
