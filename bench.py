@@ -22,7 +22,10 @@ against exact ground truth (the library's brute-force scan) is >= 0.95:
                      hipGraph, fixed ef;
   learned_batched    the same with the per-part beam width (or stopping
                      step) predicted by the network trained here on traces
-                     of 200,000 separate training queries (GPU kernels).
+                     of 200,000 separate training queries (GPU kernels);
+                     beams chosen before the search are trained for each
+                     beam cap in --ef-max (default 24 and 32), the probe
+                     forms for the largest.
 Every form's setting (its ef, or the network's calibration offset delta)
 is chosen on a held-out calibration set: 50,000 queries of the same shape
 from their own seed streams (7000+c for vectors, 8000+c for ranges), as the
@@ -76,7 +79,9 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="shrink N (default: the full workload)")
     ap.add_argument("--nq", type=int, default=None, help="shrink the query count")
     ap.add_argument("--ntrain", type=int, default=200_000, help="training traces")
-    ap.add_argument("--ef-max", type=int, default=32, help="beam of the learned form")
+    ap.add_argument("--ef-max", type=int, nargs="+", default=[24, 32],
+                    help="beam caps of the learned form: beams chosen before the search are "
+                         "trained and calibrated for each, the probe forms for the largest")
     ap.add_argument("--probe-hops", type=int, nargs="+", default=[0, 1, 4],
                     help="probe lengths of the learned form (one network each; 0: beams "
                          "chosen before the search from the selection features)")
@@ -686,7 +691,8 @@ def main():
         ef_f, cr = B.pick(ef_candidates(bkw))
         fixed_best = B.evaluate("fixed_batched", ef_f, bkw, cr)
 
-    if not args.plain_only and args.ef_max < k:
+    caps = sorted(c for c in args.ef_max if c >= k)
+    if not args.plain_only and not caps:
         log(f"learned form skipped: --ef-max {args.ef_max} < k = {k}")
     elif not args.plain_only:
         # ---- learned: traces of separate training queries, GPU training ------------------
@@ -702,31 +708,32 @@ def main():
             for target, grid in (("ef", LABEL_EF_GRID), ("hops", LABEL_HOP_GRID)):
                 if (args.target and target != args.target) or (probe == 0 and target == "hops"):
                     continue                 # a stopping step needs a probe
-                t1 = time.time()
-                g = [v for v in grid if target == "hops" or v <= args.ef_max]
-                F, T = learned.traces(ix, Qt, lt, rt, k, g, args.ef_max, probe, tkw, gt_dt,
-                                      target=target)
-                params, hist = learned.train(F, T)
-                train_info[f"{target}_probe{probe}"] = dict(
-                    traces=int(F.shape[0]), queries=args.ntrain, first_mse=round(hist[0], 4),
-                    final_mse=round(hist[-1], 4), seconds=round(time.time() - t1, 2))
-                log(f"learned target={target} probe={probe}: {F.shape[0]} part traces, mse "
-                    f"{hist[0]:.3f} -> {hist[-1]:.3f} in {time.time() - t1:.1f}s")
-                nets.append((target, probe, params))
-                del F, T
+                for cap in (caps if probe == 0 else caps[-1:]):
+                    t1 = time.time()
+                    g = [v for v in grid if target == "hops" or v <= cap]
+                    F, T = learned.traces(ix, Qt, lt, rt, k, g, cap, probe, tkw, gt_dt,
+                                          target=target)
+                    params, hist = learned.train(F, T)
+                    name = f"{target}_probe{probe}" + (f"_cap{cap}" if probe == 0 else "")
+                    train_info[name] = dict(
+                        traces=int(F.shape[0]), queries=args.ntrain, first_mse=round(hist[0], 4),
+                        final_mse=round(hist[-1], 4), seconds=round(time.time() - t1, 2))
+                    log(f"learned target={target} probe={probe} cap={cap}: {F.shape[0]} part "
+                        f"traces, mse {hist[0]:.3f} -> {hist[-1]:.3f} in {time.time() - t1:.1f}s")
+                    nets.append((target, probe, cap, params))
+                    del F, T
         del Qt, lt, rt, gt_dt
         travs = [bkw["traversal"]] + ([] if args.traversal else
                                       [t for t in ("bf16", "f32") if t != bkw["traversal"]])
-        for target, probe, params in nets:
+        for target, probe, cap, params in nets:
             for trav in travs:
                 kw = dict(bkw, traversal=trav, rerank=trav != "f32", mlp=params,
                           probe_hops=probe, mlp_target=1 if target == "hops" else 0)
                 deltas = [args.delta] if args.delta is not None else DELTA_GRID
-                dl, cr = B.pick([(dv, (lambda dv=dv: B.cal_recall(args.ef_max,
-                                                                  dict(kw, mlp_delta=dv), True)))
-                                 for dv in deltas])
+                dl, cr = B.pick([(dv, (lambda dv=dv, cap=cap: B.cal_recall(
+                    cap, dict(kw, mlp_delta=dv), True))) for dv in deltas])
                 kw["mlp_delta"] = dl
-                row = B.evaluate("learned_batched", args.ef_max, kw, cr, delta=dl, target=target,
+                row = B.evaluate("learned_batched", cap, kw, cr, delta=dl, target=target,
                                  probe_hops=probe)
                 learned_rows.append((row, kw))
         ok = [(rw, kw) for rw, kw in learned_rows if rw["recall"] >= TARGET_RECALL]
@@ -738,7 +745,7 @@ def main():
     if fixed_best is not None:
         forms.append(("fixed_batched", fixed_best["ef"], dict(bkw), fixed_best))
     if learned_best is not None:
-        forms.append(("learned_batched", args.ef_max, lkw, learned_best))
+        forms.append(("learned_batched", learned_best["ef"], lkw, learned_best))
     # the learned + batched form is the one the metric names; without it, the
     # fastest form whose evaluation recall reaches the target
     ok = [f for f in forms if f[3]["recall"] >= TARGET_RECALL]
