@@ -398,22 +398,28 @@ def embedding_eval(args, dev):
         del wt["X"]
         tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
         Qt, lt, rt = tt(wt["Q"]), tt(wt["l"]), tt(wt["r"])
-        t1 = time.time()
         _, gt_dt = learned.exact_answers(ix, Qt, lt, rt, k)
-        ef_max = 128
         lkw = dict(traversal="fp8", rerank=True)
-        F, T = learned.traces(ix, Qt, lt, rt, k, [100, 104, 112, 120, 128], ef_max, 0, lkw, gt_dt,
-                              label_recall=0.97)
-        params, hist = learned.train(F, T)
-        train_info = dict(traces=int(F.shape[0]), queries=ntr, first_mse=round(hist[0], 4),
-                          final_mse=round(hist[-1], 4), seconds=round(time.time() - t1, 1))
-        log(f"learned (beams before the search): {train_info}")
-        del F, T, Qt, lt, rt, gt_dt
-        kw = dict(lkw, mlp=params, probe_hops=0)
-        dl, cal = B.pick([(dv, (lambda dv=dv: B.cal_recall(ef_max, dict(kw, mlp_delta=dv), True)))
-                          for dv in DELTA_GRID])
-        kw["mlp_delta"] = dl
-        forms.append((B.evaluate("learned_fp8", ef_max, kw, cal, delta=dl), kw))
+        nets = []
+        train_info = {}
+        for cap in (112, 128):     # the beam cap is calibrated like the offset
+            t2 = time.time()
+            grid = [e for e in (100, 104, 112, 120, 128) if e <= cap]
+            F, T = learned.traces(ix, Qt, lt, rt, k, grid, cap, 0, lkw, gt_dt, label_recall=0.97)
+            params, hist = learned.train(F, T)
+            train_info[f"cap{cap}"] = dict(
+                traces=int(F.shape[0]), queries=ntr, first_mse=round(hist[0], 4),
+                final_mse=round(hist[-1], 4), seconds=round(time.time() - t2, 1))
+            log(f"learned (beams before the search, cap {cap}): {train_info[f'cap{cap}']}")
+            nets.append((cap, params))
+            del F, T
+        del Qt, lt, rt, gt_dt
+        for cap, params in nets:
+            kw = dict(lkw, mlp=params, probe_hops=0)
+            dl, cal = B.pick([(dv, (lambda dv=dv, cap=cap: B.cal_recall(
+                cap, dict(kw, mlp_delta=dv), True))) for dv in DELTA_GRID])
+            kw["mlp_delta"] = dl
+            forms.append((B.evaluate("learned_fp8", cap, kw, cal, delta=dl), kw))
     ok = [f for f in forms if f[0]["recall"] >= TARGET_RECALL]
     best, kw = max(ok or forms, key=lambda f: f[0]["qps"])
     ef = best["ef"]
