@@ -135,7 +135,7 @@ def test_full_batch_learned_before_search_sampled_parity(deep):
 
 def test_full_batch_scan_sampled(deep):
     """The exact scan over the whole 100,000-query batch, as the bench runs it
-    for its recall judge: 64 sampled queries equal the oracle's float32 scan
+    for its recall reference: 64 sampled queries equal the oracle's float32 scan
     bit for bit, and their top 10 agree with the float64 brute force of
     Def. 2.2 (every returned point lies within the 10th exact distance)."""
     w, gix, path = deep
