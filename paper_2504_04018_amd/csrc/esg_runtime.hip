@@ -284,28 +284,47 @@ __global__ void encode_fp8_kernel(const float* __restrict__ x, int64_t n, int32_
 }
 
 // |x|^2 per row (float32), the largest |x| and the largest relative
-// bfloat16 rounding error of any element.  One wave per row.
-__global__ void norms_kernel(const float* __restrict__ x, const uint16_t* __restrict__ xb,
-                             int64_t n, int32_t d, int32_t dp, float* __restrict__ norm2,
-                             float* __restrict__ stats) {
+// bfloat16 rounding error of any element.  One wave per row (grid-stride
+// over the rows); each workgroup reduces its waves' maxima in LDS and adds
+// one pair of atomics (per-row atomics to the same two words serialised
+// the kernel).
+__global__ __launch_bounds__(256) void norms_kernel(const float* __restrict__ x,
+                                                    const uint16_t* __restrict__ xb, int64_t n,
+                                                    int32_t d, int32_t dp, float* __restrict__ norm2,
+                                                    float* __restrict__ stats) {
   const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (row >= n) return;
-  float s = 0.0f, rel = 0.0f;
-  for (int j = lane; j < d; j += 64) {
-    const float v = x[row * dp + j];
-    s = __builtin_fmaf(v, v, s);
-    const float vb = __uint_as_float((uint32_t)xb[row * dp + j] << 16);
-    if (v != 0.0f) rel = fmaxf(rel, fabsf(vb - v) / fabsf(v));
+  const int wib = (int)(threadIdx.x >> 6), wpb = (int)(blockDim.x >> 6);
+  float mx = 0.0f, rmax = 0.0f;
+  for (int64_t row = (int64_t)blockIdx.x * wpb + wib; row < n; row += (int64_t)gridDim.x * wpb) {
+    float s = 0.0f, rel = 0.0f;
+    for (int j = lane; j < d; j += 64) {
+      const float v = x[row * dp + j];
+      s = __builtin_fmaf(v, v, s);
+      const float vb = __uint_as_float((uint32_t)xb[row * dp + j] << 16);
+      if (v != 0.0f) rel = fmaxf(rel, fabsf(vb - v) / fabsf(v));
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+      s += __shfl_xor(s, m);
+      rel = fmaxf(rel, __shfl_xor(rel, m));
+    }
+    if (lane == 0) norm2[row] = s;
+    mx = fmaxf(mx, sqrtf(s));
+    rmax = fmaxf(rmax, rel);
   }
-  for (int m = 32; m >= 1; m >>= 1) {
-    s += __shfl_xor(s, m);
-    rel = fmaxf(rel, __shfl_xor(rel, m));
-  }
+  __shared__ float smx[4], srel[4];
   if (lane == 0) {
-    norm2[row] = s;
-    atomicMax(reinterpret_cast<unsigned int*>(stats), __float_as_uint(sqrtf(s)));
-    atomicMax(reinterpret_cast<unsigned int*>(stats) + 1, __float_as_uint(rel));
+    smx[wib] = mx;
+    srel[wib] = rmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float a = 0.0f, b = 0.0f;
+    for (int w = 0; w < wpb; w++) {
+      a = fmaxf(a, smx[w]);
+      b = fmaxf(b, srel[w]);
+    }
+    atomicMax(reinterpret_cast<unsigned int*>(stats), __float_as_uint(a));
+    atomicMax(reinterpret_cast<unsigned int*>(stats) + 1, __float_as_uint(b));
   }
 }
 
@@ -828,8 +847,8 @@ int32_t esg_index_add_storage(esg_index* idx, int32_t kind, void* stream) {
     if (st != ESG_OK) return st;
     encode_bf16_kernel<<<4096, 256, 0, s>>>(idx->vec, idx->vec16, count);
     zero_i32_kernel<<<1, 64, 0, s>>>(reinterpret_cast<int32_t*>(idx->stats), 64);
-    norms_kernel<<<(unsigned)((idx->n + 3) / 4), 256, 0, s>>>(idx->vec, idx->vec16, idx->n, idx->d,
-                                                            idx->dp, idx->norm2, idx->stats);
+    norms_kernel<<<(unsigned)std::min<int64_t>(2048, (idx->n + 3) / 4), 256, 0, s>>>(
+        idx->vec, idx->vec16, idx->n, idx->d, idx->dp, idx->norm2, idx->stats);
     float host_stats[2] = {0.0f, 0.0f};
     if (hipMemcpyAsync(host_stats, idx->stats, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
