@@ -473,6 +473,8 @@ def embedding_eval(args, dev):
     torch.cuda.synchronize()
     kern_ms = float(np.mean([s_.elapsed_time(e_) for s_, e_ in ev]))
     achieved = alg_bytes / (kern_ms / 1000.0) / 1e9
+    tkey = {"traversal": kw["traversal"], "ef": ef, "learned": kw.get("mlp") is not None,
+            "mlp_delta": kw.get("mlp_delta"), "workload": "embedding", "nq": nq, "n": n}
     out = {
         "metric": f"QPS at recall@{k}>=0.95, 1 MI355X; HBM GB/s",
         "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -490,9 +492,10 @@ def embedding_eval(args, dev):
         "forms": [f[0] for f in forms],
         "sweep": B.sweep,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "search_kernel", "kernel_ms": round(kern_ms, 4),
-                     "queries_per_launch": nq, "alg_bytes_per_launch": alg_bytes},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": stored_traffic(tkey), "kernel": "search_kernel",
+                     "kernel_ms": round(kern_ms, 4), "queries_per_launch": nq,
+                     "alg_bytes_per_launch": alg_bytes, "traffic_key": tkey},
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
