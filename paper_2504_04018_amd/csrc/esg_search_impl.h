@@ -131,7 +131,12 @@ __device__ __forceinline__ float batch_dist(const SearchArgs& A, uint32_t nid, i
   constexpr int W = Traits<KIND>::W;
   constexpr int VPG = (kWave / G) < kBatch ? (kWave / G) : kBatch;  // vectors per round
   constexpr int NR = (kBatch + VPG - 1) / VPG;                       // rounds for a full batch
-  constexpr int RF0 = RFMAX / CPL;
+  // fp8 rows that take a whole wave with one chunk per lane (768 and 1,024
+  // values) keep 12 rounds in flight: a hop's dozen new vectors then need
+  // one memory round trip instead of two, within the same two waves per
+  // SIMD (measured 5 % faster at d = 768)
+  constexpr int RFK = (KIND == kFP8 && G == kWave && CPL == 1 && RFMAX == 8) ? 12 : RFMAX;
+  constexpr int RF0 = RFK / CPL;
   constexpr int RF = RF0 < 1 ? 1 : (RF0 > NR ? NR : RF0);            // rounds in flight
   const int grp = lane / G, t = lane % G;
   const int C = (A.d + W - 1) / W;
