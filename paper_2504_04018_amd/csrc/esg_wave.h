@@ -145,10 +145,10 @@ constexpr uint64_t lanes_mod_below(int g, int n) {
   return m;
 }
 
-// True in the lanes of a lane mask.  With a compile-time mask the test costs
-// no vector instruction and holds no register (the constant is rebuilt where
-// it is needed), unlike a comparison of the lane index, which the compiler
-// hoists out of every loop into a register pair.
+// True in the lanes of a lane mask.  With a compile-time mask the test needs
+// no vector instruction; a comparison of the lane index is a vector compare
+// whose result the compiler hoists out of every loop into a scalar register
+// pair, which then has to be spilled and reloaded where registers are short.
 __device__ __forceinline__ bool lane_in(uint64_t mask) {
   return __builtin_amdgcn_inverse_ballot_w64(mask);
 }
@@ -160,10 +160,6 @@ __device__ __forceinline__ bool lane_in(uint64_t mask) {
 // same result.
 __device__ __forceinline__ uint64_t cx64(uint64_t v, int j, uint64_t keep_max, int lane) {
   const uint64_t p = xor64(v, j, lane);
-  return __builtin_amdgcn_inverse_ballot_w64(ballot(v > p) ^ keep_max) ? p : v;
-}
-__device__ __forceinline__ uint32_t cx32(uint32_t v, int j, uint64_t keep_max, int lane) {
-  const uint32_t p = xor_u32(v, j, lane);
   return __builtin_amdgcn_inverse_ballot_w64(ballot(v > p) ^ keep_max) ? p : v;
 }
 
